@@ -1,0 +1,82 @@
+"""Seeded synthetic initial fields (n, eps, v) shaped like the paper's
+workloads.  This module holds no part of the scheme's arithmetic: it only
+draws fields; the library and the test oracle both take them as input.
+
+All fields are float64 arrays of shape (nz, ny, nx), x fastest.  Numerical
+units follow Sec. III of the paper: at rest n = T^3 and P = n T = T^4, so
+eps = 3 n T = 3 T^4.
+
+random_box   smooth random flow: for each component (vx, vy, vz, theta)
+             eight Fourier modes with integer wave vectors in [-4, 4]^3
+             (redrawn when zero), amplitudes U(0.5, 1) and phases U(0, 2 pi);
+             v is scaled so that max |v| = v_max exactly and
+             T = 1 + 0.1 g_theta / max |g_theta|.
+shock_tube   the Riemann problem of Sec. III: at rest, T = T_L for
+             z < nz/2 and T_R otherwise.
+tube_batch   the parameters of many shock tubes: lengths, temperature
+             ratios and eta/s drawn from a seeded generator.
+"""
+import numpy as np
+
+
+def _modes(rng, nmodes=8):
+    out = []
+    for _ in range(nmodes):
+        k = rng.integers(-4, 5, 3)
+        while not np.any(k):
+            k = rng.integers(-4, 5, 3)
+        a = rng.uniform(0.5, 1.0)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        out.append((k, a, ph))
+    return out
+
+
+def _field(modes, nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx,
+                          indexing="ij")
+    g = np.zeros((nz, ny, nx))
+    for k, a, ph in modes:
+        g += a * np.cos(2.0 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+    return g
+
+
+def random_box(nx, ny, nz, v_max, seed):
+    """Returns n, eps, vx, vy, vz for a periodic box."""
+    rng = np.random.default_rng(seed)
+    mvx, mvy, mvz, mth = (_modes(rng) for _ in range(4))
+    gx, gy, gz, gth = (_field(m, nx, ny, nz) for m in (mvx, mvy, mvz, mth))
+    norm = np.sqrt(gx * gx + gy * gy + gz * gz).max()
+    s = v_max / norm if norm > 0 else 0.0
+    vx, vy, vz = gx * s, gy * s, gz * s
+    gmax = np.abs(gth).max()
+    T = 1.0 + 0.1 * gth / (gmax if gmax > 0 else 1.0)
+    n = T ** 3
+    eps = 3.0 * T ** 4
+    return n, eps, vx, vy, vz
+
+
+def shock_tube(nz, T_left=1.0, T_right=0.8, nx=1, ny=1):
+    """Returns n, eps, vx, vy, vz for a tube at rest with a temperature step."""
+    z = np.arange(nz)
+    T1 = np.where(z < nz // 2, T_left, T_right).astype(np.float64)
+    T = np.broadcast_to(T1[:, None, None], (nz, ny, nx)).copy()
+    n = T ** 3
+    eps = 3.0 * T ** 4
+    zero = np.zeros_like(T)
+    return n, eps, zero, zero.copy(), zero.copy()
+
+
+ETA_S_CHOICES = (0.01, 0.05, 0.1, 0.2, 0.5)
+
+
+def tube_batch(ntubes, seed, n_min=200, n_max=4000):
+    """Per tube (drawn in this order): length N, temperature ratio r
+    (T_L = 1, T_R = 1/r) and eta/s."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(ntubes):
+        N = int(rng.integers(n_min, n_max + 1))
+        r = float(rng.uniform(1.1, 2.0))
+        es = float(rng.choice(ETA_S_CHOICES))
+        out.append(dict(N=N, T_left=1.0, T_right=1.0 / r, eta_s=es))
+    return out

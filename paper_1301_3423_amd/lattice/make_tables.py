@@ -1,0 +1,302 @@
+"""Offline generator of the discrete-velocity quadrature tables.
+
+The paper builds its lattice from three ingredients (Sec. II C, Eqs. dio,
+mrecon2, eqs:eqs):
+
+* spatial directions: every integer vector with |theta|^2 = R^2
+  (R^2 = 41 for the third-order model, R^2 = 9 for the second-order one,
+  Appendix A);
+* energies p0_l: the zeros of the next-order radial orthonormal polynomial,
+  R^(4)(p) for the third-order model and R^(3)(p) for the second-order one;
+  both are multiples of the generalised Laguerre polynomials L_4^(1), L_3^(1);
+* weights w_i >= 0, equal on inversion pairs, such that the discrete sums of
+  w_i g(p_i) reproduce the integrals of w(p0) g(p) d^3p/p0 for every
+  polynomial g up to degree 6 (third order) or 5 (second order).
+
+The paper keeps a vertex of that feasible set with as many zero weights as
+possible (128 of 384 points, 66 of 90) and lists it only in a supplement that
+is not available.  This script recomputes such a vertex:
+
+1. the conditions are rewritten per energy shell l as angular conditions on
+   even spherical harmonics, which is exactly equivalent and well conditioned:
+   shell sums equal the Gauss-Laguerre (alpha = 1) weights, and for harmonic
+   degree L the vectors (S_l(Y_L))_l must be orthogonal to (p_l^D)_l for
+   every degree D with L <= D <= max degree;
+2. HiGHS dual simplex with seeded random costs returns a basic feasible
+   solution (at most rank-many non-zero pair weights);
+3. the weights on that support are re-solved in 40-digit arithmetic and
+   rounded once to binary64.
+
+Among the vertices for seeds 0..NSEED-1 with the wanted number of points the
+one kept has the largest smallest weight.  The winning seed is recorded in
+the table header.  The result is written as a text table (hex floats, exact)
+and as a C initialiser for the HIP library.
+
+Run:  python make_tables.py   (needs scipy and mpmath; offline only)
+"""
+import itertools
+import hashlib
+import math
+import os
+import sys
+
+import numpy as np
+import mpmath as mp
+from scipy.optimize import linprog
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+mp.mp.dps = 40
+
+
+def directions(r2):
+    """All integer vectors with squared norm r2 (Eq. dio)."""
+    return [d for d in itertools.product(range(-7, 8), repeat=3)
+            if d[0] * d[0] + d[1] * d[1] + d[2] * d[2] == r2]
+
+
+def canonical(d):
+    """True for the member of an inversion pair whose first non-zero
+    component is positive."""
+    for x in d:
+        if x != 0:
+            return x > 0
+    raise ValueError("zero vector")
+
+
+def laguerre_nodes(order):
+    """Zeros of the radial polynomial (a multiple of L_order^(1)) and the
+    matching Gauss-Laguerre weights for the weight p e^{-p}, normalised to
+    sum to one, in 40-digit arithmetic."""
+    # L_n^(1)(p) = sum_k (-1)^k C(n+1, n-k) p^k / k!
+    coeffs = [mp.mpf((-1) ** k * math.comb(order + 1, order - k)) / math.factorial(k)
+              for k in range(order + 1)]
+    roots = sorted(mp.polyroots(list(reversed(coeffs)), maxsteps=200, extraprec=200),
+                   key=lambda z: mp.re(z))
+    roots = [mp.re(z) for z in roots]
+    # weights: sum_l W_l p_l^k = Gamma(k+2) = (k+1)! for k < order
+    V = mp.matrix(order, order)
+    b = mp.matrix(order, 1)
+    for k in range(order):
+        for l in range(order):
+            V[k, l] = roots[l] ** k
+        b[k] = mp.factorial(k + 1)
+    W = mp.lu_solve(V, b)
+    return roots, [W[l] for l in range(order)]
+
+
+def sphere_moment(a, b, c):
+    """<nx^a ny^b nz^c> over the unit sphere (uniform measure)."""
+    if a % 2 or b % 2 or c % 2:
+        return mp.mpf(0)
+    def dfact(n):
+        return mp.mpf(1) if n <= 0 else n * dfact(n - 2)
+    return dfact(a - 1) * dfact(b - 1) * dfact(c - 1) / dfact(a + b + c + 1)
+
+
+def monomials(deg):
+    return [(a, b, deg - a - b) for a in range(deg + 1) for b in range(deg + 1 - a)]
+
+
+def harmonic_basis(L):
+    """Orthonormal basis (on the sphere) of the harmonic part of degree L,
+    as coefficient vectors over monomials(L)."""
+    mons = monomials(L)
+    lower = monomials(L - 2) if L >= 2 else []
+    n = len(mons)
+    G = np.array([[float(sphere_moment(*(np.add(p, q)))) for q in mons] for p in mons])
+    # lower-degree functions embedded at degree L: m * (nx^2+ny^2+nz^2)
+    emb = []
+    for q in lower:
+        v = np.zeros(n)
+        for e in ((2, 0, 0), (0, 2, 0), (0, 0, 2)):
+            v[mons.index(tuple(np.add(q, e)))] += 1.0
+        emb.append(v)
+    # Gram-Schmidt in the sphere inner product: first the embedded lower
+    # space, then the monomials; keep what is new.
+    basis, out = [], []
+    def ip(u, v):
+        return u @ G @ v
+    for v in emb:
+        for bvec in basis:
+            v = v - ip(v, bvec) * bvec
+        nv = math.sqrt(max(ip(v, v), 0.0))
+        if nv > 1e-10:
+            basis.append(v / nv)
+    for j in range(n):
+        v = np.zeros(n)
+        v[j] = 1.0
+        for _ in range(2):
+            for bvec in basis + out:
+                v = v - ip(v, bvec) * bvec
+        nv = math.sqrt(max(ip(v, v), 0.0))
+        if nv > 1e-8:
+            out.append(v / nv)
+    assert len(out) == 2 * L + 1, (L, len(out))
+    return mons, out
+
+
+def eval_poly(mons, coef, n):
+    return sum(c * n[0] ** m[0] * n[1] ** m[1] * n[2] ** m[2] for m, c in zip(mons, coef))
+
+
+def constraint_system(r2, nshell, maxdeg):
+    """Rows of the well-conditioned equality system over pair weights u[l,k]
+    (l shell, k canonical direction).  Each pair stands for two points with
+    weight u each."""
+    dirs = [d for d in directions(r2) if canonical(d)]
+    R = math.sqrt(r2)
+    nvec = [np.array(d, float) / R for d in dirs]
+    p0, W = laguerre_nodes(nshell)
+    p0f = np.array([float(x) for x in p0])
+    nd = len(dirs)
+    nvar = nshell * nd
+    rows, rhs = [], []
+    # shell sums
+    for l in range(nshell):
+        r = np.zeros(nvar)
+        r[l * nd:(l + 1) * nd] = 2.0
+        rows.append(r)
+        rhs.append(float(W[l]))
+    for L in range(2, maxdeg + 1, 2):
+        mons, H = harmonic_basis(L)
+        # radial combinations that must vanish: span{p^D : L <= D <= maxdeg}
+        P = np.array([[p0f[l] ** D for l in range(nshell)] for D in range(L, maxdeg + 1)])
+        P = P / np.abs(P).max(axis=1, keepdims=True)
+        U_, s_, Vt = np.linalg.svd(P, full_matrices=False)
+        rank = int((s_ > 1e-12 * s_[0]).sum())
+        radial = Vt[:rank]
+        for Y in H:
+            yk = np.array([2.0 * eval_poly(mons, Y, n) for n in nvec])
+            for rv in radial:
+                r = np.zeros(nvar)
+                for l in range(nshell):
+                    r[l * nd:(l + 1) * nd] = rv[l] * yk
+                rows.append(r)
+                rhs.append(0.0)
+    return dirs, p0, W, np.array(rows), np.array(rhs)
+
+
+def polish(dirs, p0, W, A, b, support, r2):
+    """Re-solve the square (or tall) system restricted to the support in
+    high precision: least squares via mpmath QR normal equations."""
+    As = mp.matrix(A[:, support].tolist())
+    bs = mp.matrix(b.tolist())
+    x = mp.lu_solve(As.T * As, As.T * bs)
+    return [x[j] for j in range(len(support))]
+
+
+def exactness_residual(points, weights, maxdeg):
+    """max |sum_i w_i p_i^a - integral| over all monomials of degree <= maxdeg
+    in (p0, px, py, pz), relative to the size of the integral."""
+    worst = 0.0
+    P = np.array(points)
+    w = np.array(weights)
+    for D in range(maxdeg + 1):
+        for a0 in range(D + 1):
+            for (a, b_, c) in monomials(D - a0):
+                exact = float(mp.factorial(D + 1) * sphere_moment(a, b_, c))
+                num = float(np.sum(w * P[:, 0] ** a0 * P[:, 1] ** a * P[:, 2] ** b_ * P[:, 3] ** c))
+                scale = float(mp.factorial(D + 1))
+                worst = max(worst, abs(num - exact) / scale)
+    return worst
+
+
+def build_vertex(r2, nshell, maxdeg, seed):
+    dirs, p0, W, A, b = constraint_system(r2, nshell, maxdeg)
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, A.shape[1])
+    res = linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs-ds")
+    if res.status != 0:
+        return None
+    u = res.x
+    support = [j for j in range(len(u)) if u[j] > 1e-12]
+    upol = polish(dirs, p0, W, A, b, support, r2)
+    if min(upol) <= 0:
+        return None
+    nd = len(dirs)
+    R = mp.sqrt(r2)
+    pts = []
+    for j, uj in zip(support, upol):
+        l, k = divmod(j, nd)
+        d = dirs[k]
+        for sgn in (1, -1):
+            th = tuple(sgn * x for x in d)
+            pts.append(dict(shell=l, theta=th, p0=p0[l], w=uj))
+    return dict(points=pts, p0=p0, W=W, seed=seed)
+
+
+def order_points(points):
+    """Order: by shell, then canonical direction; each pair (canonical,
+    inverse) sits at indices (2k, 2k+1) so that the inverse of i is i^1."""
+    canon = [p for p in points if canonical(p['theta'])]
+    canon.sort(key=lambda p: (p['shell'], tuple(-abs(x) for x in p['theta']), p['theta']))
+    out = []
+    for p in canon:
+        inv = next(q for q in points if q['shell'] == p['shell']
+                   and q['theta'] == tuple(-x for x in p['theta']))
+        out.append(p)
+        out.append(inv)
+    return out
+
+
+def write_tables(name, r2, nshell, maxdeg, vertex, note):
+    pts = order_points(vertex['points'])
+    R = mp.sqrt(r2)
+    lines = []
+    lines.append("# %s quadrature table for the relativistic lattice Boltzmann model" % name)
+    lines.append("# R^2 = %d, shells = %d, exact for polynomials of degree <= %d" % (r2, nshell, maxdeg))
+    lines.append("# points = %d, LP seed = %d, generated by make_tables.py" % (len(pts), vertex['seed']))
+    lines.append("# %s" % note)
+    lines.append("# columns: i inv shell tx ty tz p0(hex) w(hex) p0(dec) w(dec)")
+    for i, p in enumerate(pts):
+        p0 = float(p['p0'])
+        w = float(p['w'])
+        lines.append("%d %d %d %d %d %d %s %s %.17g %.17g" % (
+            i, i ^ 1, p['shell'], p['theta'][0], p['theta'][1], p['theta'][2],
+            p0.hex(), w.hex(), p0, w))
+    text = "\n".join(lines) + "\n"
+    txt = os.path.join(HERE, "%s.txt" % name)
+    with open(txt, "w") as fh:
+        fh.write(text)
+    sha = hashlib.sha256(text.encode()).hexdigest()
+    # C initialiser for the HIP library (same numbers, exact hex literals)
+    inc = [
+        "/* %s quadrature table: generated by make_tables.py from %s.txt" % (name, name),
+        " * (sha256 %s). Each row: {tx, ty, tz, shell, p0, w}. */" % sha,
+    ]
+    for p in pts:
+        inc.append("{%d, %d, %d, %d, %s, %s}," % (
+            p['theta'][0], p['theta'][1], p['theta'][2], p['shell'],
+            float(p['p0']).hex(), float(p['w']).hex()))
+    with open(os.path.join(HERE, "%s.inc" % name), "w") as fh:
+        fh.write("\n".join(inc) + "\n")
+    return txt, sha
+
+
+def search(name, r2, nshell, maxdeg, nseed, want_points):
+    """Vertices for seeds 0..nseed-1; keep those with the wanted number of
+    points whose polished weights meet every condition to 1e-13, and return
+    the one with the largest smallest weight (the best-conditioned choice)."""
+    best = None
+    for seed in range(nseed):
+        v = build_vertex(r2, nshell, maxdeg, seed)
+        if v is None:
+            continue
+        pts = v['points']
+        res = exactness_residual(
+            [[float(p['p0'])] + [float(p['p0']) * t / math.sqrt(r2) for t in p['theta']] for p in pts],
+            [float(p['w']) for p in pts], maxdeg)
+        wmin = min(float(p['w']) for p in pts)
+        print("seed %3d  points %3d  resid %.1e  min w %.3e" % (seed, len(pts), res, wmin), flush=True)
+        if res > 1e-13 or len(pts) != want_points:
+            continue
+        if best is None or wmin > best[0]:
+            best = (wmin, v)
+    return best[1]
+
+
+if __name__ == "__main__":
+    nseed = int(sys.argv[1]) if len(sys.argv) > 1 else 64
+    v3 = search("d3q128", 41, 4, 6, nseed, 128)
+    print(write_tables("d3q128", 41, 4, 6, v3,
+                       "third-order model (R = sqrt(41), degree <= 6)"))

@@ -1,0 +1,55 @@
+"""A second, deliberately naive implementation of one step of Eq. rlb:disc
+for tiny lattices: pure-Python loops over cells and populations, LAPACK's
+eigen-solver for the Landau-Lifshitz frame and the closed-form equilibrium
+of Appendix B (Eq. equi3rd).  It shares nothing with the oracle except the
+lattice table, and exists to pin the oracle on small cases."""
+import math
+
+import numpy as np
+
+from appendix_equilibrium import equi3rd
+
+ETA = np.diag([1.0, -1.0, -1.0, -1.0])
+
+
+def landau_eig(Tm):
+    w, V = np.linalg.eig(Tm @ ETA)
+    for j in range(4):
+        u = V[:, j].real
+        nrm = u @ ETA @ u
+        if nrm > 0 and abs(w[j].imag) < 1e-12 * abs(w[j].real):
+            u = u / math.sqrt(nrm)
+            if u[0] < 0:
+                u = -u
+            return w[j].real, u
+    raise RuntimeError("no timelike eigenvector")
+
+
+def step(lat, f, shape, tau=None, eta_s=None):
+    """f[Q][nz][ny][nx] (numpy) -> new array after collide + push."""
+    nz, ny, nx = shape
+    Q = lat.Q
+    out = np.zeros_like(f)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                fc = [f[i, z, y, x] for i in range(Q)]
+                N = np.zeros(4)
+                Tm = np.zeros((4, 4))
+                for i in range(Q):
+                    N += fc[i] * lat.p[i]
+                    Tm += fc[i] * np.outer(lat.p[i], lat.p[i])
+                eps, U = landau_eig(Tm)
+                n = U @ ETA @ N
+                T = eps / (3 * n)
+                if tau is not None:
+                    t = tau
+                else:
+                    t = 0.5 + 1.5 * lat.R / T * eta_s * (4 - math.log(n / T**3))
+                for i in range(Q):
+                    feq = equi3rd(n, T, U, lat.p[i], lat.w[i])
+                    pU = lat.p[i] @ ETA @ U
+                    fs = fc[i] - pU / (t * lat.p[i, 0]) * (fc[i] - feq)
+                    tx, ty, tz = (int(a) for a in lat.theta[i])
+                    out[i, (z + tz) % nz, (y + ty) % ny, (x + tx) % nx] = fs
+    return out
