@@ -1,0 +1,148 @@
+"""Throughput of the fused RLBD stream-and-collide step on one MI355X.
+
+Headline workload: a 256^3 periodic box in mixed precision (float32
+populations; moments, Landau frame and equilibrium coefficients in
+float64), smooth random fields with |v| <= 0.6 and eta/s = 0.5.  The same
+box is also timed in full float64.  A step is one launch of the fused
+gather-moments-Landau-equilibrium-collision kernel over every cell; inputs
+are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  --gpus > 1 is not supported: the program
+runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, REPO)
+
+HBM_PEAK_GBS = 8000.0
+Q = 128
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--edge", type=int, default=256)
+    ap.add_argument("--vmax", type=float, default=0.6)
+    ap.add_argument("--eta-s", type=float, default=0.5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(solver, steps, warmup):
+    """Average per-step time (ms) from HIP events on the solver's stream."""
+    import torch
+    st = solver.stream
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    solver.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def run_box(edge, precision, fields, steps, warmup, eta_s):
+    from paper_1301_3423_amd import rlb
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
+    s.init_fields(*fields)
+    ms, wall = time_steps(s, steps, warmup)
+    flags, t = s.status()
+    cells = edge ** 3
+    b = 8 if precision == "fp64" else 4
+    bytes_per_launch = 2 * Q * b * cells
+    out = dict(ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, wall_s=wall, flags=flags,
+               achieved_gbs=bytes_per_launch / (ms * 1e-3) / 1e9, bytes_per_launch=bytes_per_launch)
+    del s
+    return out
+
+
+def cpu_baseline(vmax, eta_s):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from oracle import rlb as orlb
+    from paper_1301_3423_amd import inputs
+    edge, steps = 48, 3
+    with threadpool_limits(limits=1):
+        lat = oracle.load_lattice()
+        o = orlb.Solver(edge, edge, edge, lat=lat, eta_s=eta_s)
+        o.init_fields(*inputs.random_box(edge, edge, edge, vmax, seed=3))
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+    return dict(value=edge ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample="%d^3 box, same field generator (v_max %.2g, eta/s %.2g), %d steps, numpy FP64, "
+                       "BLAS limited to 1 thread; %.1f s" % (edge, vmax, eta_s, steps, dt))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1301_3423_amd import inputs
+    torch.cuda.set_device(0)
+    edge = args.edge
+    print("bench: generating %d^3 fields" % edge, file=sys.stderr, flush=True)
+    fields = inputs.random_box(edge, edge, edge, args.vmax, seed=3)
+    print("bench: mixed precision", file=sys.stderr, flush=True)
+    mixed = run_box(edge, "mixed", fields, args.steps, args.warmup, args.eta_s)
+    print("bench: mixed %.1f MLUPS" % mixed["mlups"], file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_box(edge, "fp64", fields, args.steps, args.warmup, args.eta_s)
+        print("bench: fp64 %.1f MLUPS" % fp64["mlups"], file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else cpu_baseline(args.vmax, args.eta_s)
+    line = {
+        "metric": "MLUPS at 256^3 FP64 vs FP32-mixed (% HBM roofline); served p50/p99 latency",
+        "value": round(mixed["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "3D periodic box %d^3, mixed precision (float32 populations, float64 "
+                               "moments/Landau frame), random fields |v|<=%.2g, T=1+-10%%, eta/s=%.2g"
+                               % (edge, args.vmax, args.eta_s),
+                   "cells": edge ** 3, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(mixed["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(mixed["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "status_flags": mixed["flags"],
+    }
+    if fp64 is not None:
+        line["fp64"] = {"value": round(fp64["mlups"], 2), "unit": "MLUPS", "dtype": "f64",
+                        "ms_per_step": round(fp64["ms_per_step"], 4),
+                        "roofline": {"bound": "hbm", "achieved": round(fp64["achieved_gbs"], 1),
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(fp64["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None},
+                        "status_flags": fp64["flags"],
+                        "mixed_over_fp64": round(mixed["mlups"] / fp64["mlups"], 3)}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * rlb.h -- C ABI of the MI355X library for the third-order relativistic
+ * lattice Boltzmann scheme (RLBD) of Mendoza, Karlin, Succi and Herrmann,
+ * "Relativistic Lattice Boltzmann Model with Improved Dissipation".
+ *
+ * What one step computes (Sec. II D, Eq. rlb:disc, time step delta t' = 1):
+ *
+ *   f_i(x + theta_i, t + 1) = f_i(x, t)
+ *                             - (p_i^mu U_mu / (tau p_i^0)) (f_i - f_i^eq)
+ *
+ * on a periodic nx x ny x nz cubic lattice, with 128 discrete 4-momenta
+ * p_i = p0_i (1, theta_i / R), R = sqrt(41) (Sec. II C, Eqs. dio, mrecon2).
+ * Per cell: the moments N^mu = sum f_i p_i^mu and T^{mu nu} =
+ * sum f_i p_i^mu p_i^nu; the Landau-Lifshitz eigenproblem
+ * T^{mu nu} U_nu = eps U^mu (Eq. eigenproblem); n = U_mu N^mu; the equation
+ * of state eps = 3 n T, P = eps / 3; the Maxwell-Juttner equilibrium
+ * projected on the orthonormal polynomials of Table I up to third order
+ * (Eqs. coeff, disc1); and the Anderson-Witting relaxation.
+ *
+ * Conventions
+ *  - Every call returns RLB_OK (0) or a negative error code; no C++
+ *    exception crosses this interface.  rlb_strerror() names a code and
+ *    rlb_last_error() gives the last message of the calling thread.
+ *  - Fields are float64 arrays of nx*ny*nz entries, x fastest:
+ *    index = x + nx * (y + ny * z).
+ *  - "stream" arguments are hipStream_t values passed as void*; NULL is the
+ *    default stream.  The library never synchronises the device except
+ *    where a call says so.
+ *  - The caller owns every device buffer it passes (e.g. memory of a torch
+ *    tensor) and must keep it alive until rlb_destroy; the library frees
+ *    only its own small host allocations.
+ *  - A solver is bound to one stream and one device and is not
+ *    thread-safe; use one solver per thread.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define RLB_OK 0
+#define RLB_EINVAL (-1)   /* bad argument (sizes, modes, tau <= 1/2, NULL) */
+#define RLB_ENOMEM (-2)   /* caller buffer smaller than rlb_state_bytes()   */
+#define RLB_ENONPHYS (-3) /* init field with n<=0, eps<=0, |v|>=1 or NaN   */
+#define RLB_EHIP (-4)     /* HIP runtime or launch error                    */
+#define RLB_ESTATE (-5)   /* call out of order (e.g. step before init)      */
+#define RLB_EIO (-6)      /* checkpoint file could not be written or read   */
+
+/* ---- precision of the stored populations ------------------------------- */
+#define RLB_FP64 0  /* populations, moments and equilibrium in float64       */
+#define RLB_MIXED 1 /* populations stored and streamed as float32; moments
+                       accumulated in float64 from the float32 values; the
+                       Landau solve, gamma, tau and the equilibrium
+                       coefficients in float64; equilibrium and relaxation of
+                       each population in float32                            */
+
+/* ---- relaxation time ---------------------------------------------------- */
+#define RLB_TAU_FIXED 0 /* tau is a constant (> 1/2)                         */
+#define RLB_TAU_ETA_S 1 /* tau per cell and step from eta/s:
+                           eta = (2/3) n T (tau - 1/2) / R and
+                           s = 4 n - n ln(n / n_eq) with n_eq = T^3
+                           (Sec. II D transport coefficients, Sec. III), i.e.
+                           tau = 1/2 + (3R/(2T)) (eta/s) (4 - ln(n/T^3))     */
+
+/* ---- status flags (sticky, OR-ed by the kernels) ----------------------- */
+#define RLB_FLAG_NONFINITE 1u   /* a cell produced a NaN or infinity        */
+#define RLB_FLAG_NONPHYSICAL 2u /* n <= 0, eps <= 0 or |v| >= 1 in a cell   */
+#define RLB_FLAG_LANDAU 4u      /* the Landau-frame solve did not converge  */
+
+#define RLB_MAX_Q 128
+
+/* The discrete velocity set: 128 points on 4 energy shells (Sec. II C).
+ * theta: integer displacement per step; p0: energy; w: weight;
+ * inv[i]: index of the point with theta = -theta_i on the same shell (the
+ * library orders points so that inv[i] == i ^ 1); shell: 0..3.  The weights
+ * were recomputed from the paper's conditions (Eqs. eqs:eqs) because the
+ * paper lists them only in a supplement; sha256 is that of the text table
+ * they come from. */
+typedef struct rlb_lattice {
+  int32_t q;
+  int32_t r2;
+  int32_t nshell;
+  int8_t theta[RLB_MAX_Q][3];
+  double p0[RLB_MAX_Q];
+  double w[RLB_MAX_Q];
+  int32_t inv[RLB_MAX_Q];
+  int32_t shell[RLB_MAX_Q];
+  char sha256[65];
+} rlb_lattice_t;
+
+/* Fills *out with the library's lattice.  Read-only library data. */
+int rlb_lattice_info(rlb_lattice_t *out);
+
+/* ---- one periodic box ---------------------------------------------------- */
+typedef struct rlb_config {
+  int32_t nx, ny, nz; /* lattice size, all periodic; each >= 1            */
+  int32_t precision;  /* RLB_FP64 or RLB_MIXED                            */
+  int32_t tau_mode;   /* RLB_TAU_FIXED or RLB_TAU_ETA_S                   */
+  double tau;         /* relaxation time when tau_mode == RLB_TAU_FIXED   */
+  double eta_s;       /* eta/s (> 0) when tau_mode == RLB_TAU_ETA_S        */
+} rlb_config;
+
+typedef struct rlb_solver rlb_solver;
+
+/* Bytes of device memory a box of this size needs: two population buffers
+ * (the kernels read one and write the other) plus a 4 KiB status area.
+ * Returns 0 for invalid sizes or precision.  Pure function. */
+size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision);
+
+/* Creates a solver over caller-owned device memory d_buf of `bytes` bytes
+ * (>= rlb_state_bytes, 256-byte aligned) on `stream` of the current device.
+ * Errors: RLB_EINVAL (bad config / NULL / misaligned), RLB_ENOMEM (bytes too
+ * small), RLB_EHIP.  No device work is issued. */
+int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t bytes,
+               void *stream);
+
+/* Sets every cell to local equilibrium f_i = f_i^eq(n, T, U) with
+ * T = eps / (3 n) and U = gamma (1, v) (initial states of Sec. III) and
+ * resets t = 0 and the status flags.  n, eps, vx, vy, vz are nx*ny*nz
+ * float64 values.  on_device = 0: host arrays, validated on the host
+ * (RLB_ENONPHYS if any n <= 0, eps <= 0, |v| >= 1 or a value is not
+ * finite; nothing is changed then) and copied through the idle population
+ * buffer; the call returns after the copy.  on_device = 1: device arrays,
+ * read on the stream; invalid cells raise RLB_FLAG_NONPHYSICAL instead.
+ * The arrays may be released when the call returns (host) or when the
+ * stream has passed this point (device). */
+int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const double *vx,
+                    const double *vy, const double *vz, int32_t on_device);
+
+/* Advances nsteps >= 0 time steps; asynchronous on the solver's stream.
+ * RLB_ESTATE before rlb_init_fields, RLB_EHIP on a launch error. */
+int rlb_step(rlb_solver *s, int64_t nsteps);
+
+/* Macroscopic fields of the current (post-streaming, pre-collision) state:
+ * n, eps, P each nx*ny*nz values and U4 = 4*nx*ny*nz values laid out as
+ * U^0 block, U^1 block, U^2 block, U^3 block.  Any output pointer may be
+ * NULL.  on_device = 0: host arrays, the call synchronises the stream;
+ * on_device = 1: device arrays written on the stream (no synchronisation). */
+int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P,
+                    int32_t on_device);
+
+/* Box totals of N^0 and T^{0 nu} (nu = 0..3) of the current state, the
+ * quantities the scheme conserves (Eqs. conser1, conser2): out[0] = N^0,
+ * out[1..4] = T^{00}, T^{01}, T^{02}, T^{03}.  Float64 sums with a fixed
+ * reduction order; synchronises the stream. */
+int rlb_conserved(rlb_solver *s, double out[5]);
+
+/* Sticky status flags (RLB_FLAG_*) and the current step count.  Either
+ * pointer may be NULL.  Synchronises the stream. */
+int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t);
+
+/* Writes the raw populations, t, the flags and the configuration to a file
+ * (host I/O; synchronises the stream). */
+int rlb_save(rlb_solver *s, const char *path);
+
+/* Restores a state written by rlb_save into a solver with the same
+ * configuration.  RLB_EINVAL if the file's configuration or lattice
+ * differs, RLB_EIO on a short or unreadable file. */
+int rlb_load(rlb_solver *s, const char *path);
+
+/* Releases the solver's host allocations (not the caller's buffer). */
+void rlb_destroy(rlb_solver *s);
+
+/* ---- diagnostics --------------------------------------------------------- */
+const char *rlb_strerror(int code);
+const char *rlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLB_H */

@@ -270,6 +270,8 @@ def write_tables(name, r2, nshell, maxdeg, vertex, note):
             float(p['p0']).hex(), float(p['w']).hex()))
     with open(os.path.join(HERE, "%s.inc" % name), "w") as fh:
         fh.write("\n".join(inc) + "\n")
+    with open(os.path.join(HERE, "%s.sha" % name), "w") as fh:
+        fh.write('"%s"\n' % sha)
     return txt, sha
 
 

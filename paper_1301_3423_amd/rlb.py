@@ -1,0 +1,207 @@
+"""Thin ctypes binding of the C ABI in include/rlb.h (argument marshalling
+only: every step of the update runs in the HIP library).  PyTorch provides
+the device memory and the stream.
+
+    from paper_1301_3423_amd import rlb
+    s = rlb.Solver(64, 64, 64, precision="fp64", eta_s=0.2)
+    s.init_fields(n, eps, vx, vy, vz)        # numpy (host) or torch (device)
+    s.step(100)
+    out = s.read_fields()                    # dict of numpy arrays
+
+The library is loaded on first use; if librlb.so is missing this raises
+instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librlb.so")
+
+OK, EINVAL, ENOMEM, ENONPHYS, EHIP, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+TAU_FIXED, TAU_ETA_S = 0, 1
+FLAG_NONFINITE, FLAG_NONPHYSICAL, FLAG_LANDAU = 1, 2, 4
+MAX_Q = 128
+
+# every symbol include/rlb.h declares
+EXPORTS = ("rlb_lattice_info", "rlb_state_bytes", "rlb_create", "rlb_init_fields", "rlb_step",
+           "rlb_read_fields", "rlb_conserved", "rlb_status", "rlb_save", "rlb_load", "rlb_destroy",
+           "rlb_strerror", "rlb_last_error")
+
+
+class RLBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_name(code), code, msg))
+        self.code = code
+
+
+def _name(code):
+    return {OK: "RLB_OK", EINVAL: "RLB_EINVAL", ENOMEM: "RLB_ENOMEM", ENONPHYS: "RLB_ENONPHYS",
+            EHIP: "RLB_EHIP", ESTATE: "RLB_ESTATE", EIO: "RLB_EIO"}.get(code, "RLB_?")
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("r2", ctypes.c_int32), ("nshell", ctypes.c_int32),
+                ("theta", (ctypes.c_int8 * 3) * MAX_Q), ("p0", ctypes.c_double * MAX_Q),
+                ("w", ctypes.c_double * MAX_Q), ("inv", ctypes.c_int32 * MAX_Q),
+                ("shell", ctypes.c_int32 * MAX_Q), ("sha256", ctypes.c_char * 65)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librlb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librlb.so is not built: run python -m paper_1301_3423_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64
+        L.rlb_lattice_info.argtypes = [ctypes.POINTER(Lattice)]
+        L.rlb_state_bytes.argtypes = [i32, i32, i32, i32]
+        L.rlb_state_bytes.restype = ctypes.c_size_t
+        L.rlb_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, vp]
+        L.rlb_init_fields.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+        L.rlb_step.argtypes = [vp, i64]
+        L.rlb_read_fields.argtypes = [vp, vp, vp, vp, vp, i32]
+        L.rlb_conserved.argtypes = [vp, dp]
+        L.rlb_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64)]
+        L.rlb_save.argtypes = [vp, ctypes.c_char_p]
+        L.rlb_load.argtypes = [vp, ctypes.c_char_p]
+        L.rlb_destroy.argtypes = [vp]
+        L.rlb_destroy.restype = None
+        L.rlb_strerror.argtypes = [ctypes.c_int]
+        L.rlb_strerror.restype = ctypes.c_char_p
+        L.rlb_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != OK:
+        raise RLBError(rc, lib().rlb_last_error().decode())
+    return rc
+
+
+def lattice_info():
+    lat = Lattice()
+    check(lib().rlb_lattice_info(ctypes.byref(lat)))
+    q = lat.q
+    return dict(q=q, r2=lat.r2, nshell=lat.nshell,
+                theta=np.array([[lat.theta[i][k] for k in range(3)] for i in range(q)], dtype=np.int64),
+                p0=np.array(lat.p0[:q]), w=np.array(lat.w[:q]), inv=np.array(lat.inv[:q]),
+                shell=np.array(lat.shell[:q]), sha256=lat.sha256.decode())
+
+
+def state_bytes(nx, ny, nz, precision="fp64"):
+    return lib().rlb_state_bytes(nx, ny, nz, _prec(precision))
+
+
+def _prec(p):
+    if p in ("fp64", FP64):
+        return FP64
+    if p in ("mixed", MIXED):
+        return MIXED
+    raise ValueError("precision must be 'fp64' or 'mixed'")
+
+
+def _stream_ptr(stream):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+class Solver:
+    """One periodic nx x ny x nz box on the current HIP device.
+
+    Device memory is a torch uint8 tensor owned by this object; the solver
+    runs on `stream` (default: torch's current stream at construction)."""
+
+    def __init__(self, nx, ny, nz, precision="fp64", tau=None, eta_s=None, stream=None, device=None):
+        import torch
+        if (tau is None) == (eta_s is None):
+            raise ValueError("give exactly one of tau, eta_s")
+        self.shape = (nz, ny, nx)
+        self.cells = nx * ny * nz
+        self.precision = precision
+        cfg = Config(nx, ny, nz, _prec(precision), TAU_FIXED if tau is not None else TAU_ETA_S,
+                     float(tau) if tau is not None else 0.0, float(eta_s) if eta_s is not None else 0.0)
+        self.cfg = cfg
+        nbytes = state_bytes(nx, ny, nz, precision)
+        if nbytes == 0:
+            raise RLBError(EINVAL, "invalid lattice size or precision")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().rlb_create(ctypes.byref(h), ctypes.byref(cfg), ctypes.c_void_p(self.buffer.data_ptr()),
+                               nbytes, _stream_ptr(self.stream)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rlb_destroy(h)
+            self._h = None
+
+    # -- fields -------------------------------------------------------------
+    def init_fields(self, n, eps, vx, vy, vz):
+        import torch
+        arrs = (n, eps, vx, vy, vz)
+        if all(isinstance(a, torch.Tensor) and a.is_cuda for a in arrs):
+            ts = [a.contiguous().to(torch.float64) for a in arrs]
+            for t in ts:
+                if t.numel() != self.cells:
+                    raise ValueError("field has %d values, expected %d" % (t.numel(), self.cells))
+            check(lib().rlb_init_fields(self._h, *[ctypes.c_void_p(t.data_ptr()) for t in ts], 1))
+            self._keep = ts          # alive until the stream has consumed them
+            return
+        hs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)).ravel() for a in arrs]
+        for h in hs:
+            if h.size != self.cells:
+                raise ValueError("field has %d values, expected %d" % (h.size, self.cells))
+        check(lib().rlb_init_fields(self._h, *[ctypes.c_void_p(h.ctypes.data) for h in hs], 0))
+
+    def step(self, nsteps=1):
+        check(lib().rlb_step(self._h, int(nsteps)))
+
+    def read_fields(self, on_device=False):
+        """n, eps, P (cells,) and U (4, cells) of the current state."""
+        C = self.cells
+        if on_device:
+            import torch
+            out = dict(n=torch.empty(C, dtype=torch.float64, device=self.device),
+                       eps=torch.empty(C, dtype=torch.float64, device=self.device),
+                       U=torch.empty(4, C, dtype=torch.float64, device=self.device),
+                       P=torch.empty(C, dtype=torch.float64, device=self.device))
+            check(lib().rlb_read_fields(self._h, *[ctypes.c_void_p(out[k].data_ptr()) for k in ("n", "eps", "U", "P")], 1))
+            return out
+        out = dict(n=np.empty(C), eps=np.empty(C), U=np.empty((4, C)), P=np.empty(C))
+        check(lib().rlb_read_fields(self._h, *[ctypes.c_void_p(out[k].ctypes.data) for k in ("n", "eps", "U", "P")], 0))
+        return out
+
+    def conserved(self):
+        out = (ctypes.c_double * 5)()
+        check(lib().rlb_conserved(self._h, out))
+        return np.array(out[:])
+
+    def status(self):
+        fl = ctypes.c_uint32()
+        t = ctypes.c_int64()
+        check(lib().rlb_status(self._h, ctypes.byref(fl), ctypes.byref(t)))
+        return fl.value, t.value
+
+    def save(self, path):
+        check(lib().rlb_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        check(lib().rlb_load(self._h, str(path).encode()))

@@ -1,0 +1,133 @@
+"""Parity of the HIP library with the FP64 oracle, through the C ABI.
+
+Bar: max-norm relative error per field (n, eps, U^0..U^3, P) <= 1e-12 for
+the FP64 path and <= 1e-5 for the mixed path (float32 populations)."""
+import numpy as np
+import pytest
+
+from gpu_util import field_errors, note, run_pair
+from oracle import rlb as orlb
+from paper_1301_3423_amd import inputs, rlb
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+# Small random boxes are far from hydrodynamic (wave lengths of a few
+# cells), so their velocity fields decay quickly; a max-norm error relative
+# to a field that has decayed to ~1e-3 of its start amplifies rounding.
+# The step counts below keep every case well conditioned: perturbing the
+# oracle's populations by 1e-15 moves its fields by < 2e-14 here.
+CASES = [
+    # (nx, ny, nz), v_max, steps, relaxation
+    ((13, 11, 7), 0.5, 12, dict(eta_s=0.2)),     # 1001 cells: 4 blocks, ragged tail
+    ((24, 16, 10), 0.6, 3, dict(tau=0.9)),       # 15 blocks, every axis > 6
+    ((5, 4, 3), 0.4, 6, dict(eta_s=0.1)),        # every axis < 7: wrap beyond the edge
+    ((9, 1, 17), 0.5, 4, dict(tau=1.3)),         # a degenerate axis of size 1
+    ((1, 1, 1), 0.3, 3, dict(tau=0.7)),          # a single cell
+    ((40, 36, 33), 0.5, 10, dict(eta_s=0.2)),    # 47520 cells: 186 blocks, ragged tail
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,vmax,steps,relax", CASES)
+def test_box_parity(lat, shape, vmax, steps, relax, precision):
+    fields = inputs.random_box(*shape, vmax, seed=sum(shape))
+    gpu, ref, flags, t, _, _ = run_pair(lat, shape, fields, steps, precision, **relax)
+    err = field_errors(gpu, ref)
+    note("errors %s" % {k: "%.2e" % v for k, v in err.items()})
+    assert flags == 0 and t == steps
+    assert max(err.values()) <= TOL[precision], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shock_tube_config(lat, precision):
+    """The 1x1x200 Riemann problem (T 1.0 / 0.8, eta/s = 0.1), 200 steps."""
+    fields = inputs.shock_tube(200, 1.0, 0.8)
+    gpu, ref, flags, t, _, _ = run_pair(lat, (1, 1, 200), fields, 200, precision, eta_s=0.1)
+    err = field_errors(gpu, ref)
+    note("errors %s" % {k: "%.2e" % v for k, v in err.items()})
+    assert flags == 0
+    assert max(err.values()) <= TOL[precision], err
+
+
+def test_read_at_t0_returns_init(lat):
+    fields = inputs.random_box(10, 9, 8, 0.6, seed=3)
+    s = rlb.Solver(10, 9, 8, precision="fp64", tau=1.0)
+    s.init_fields(*fields)
+    out = s.read_fields()
+    n, eps, vx, vy, vz = (np.asarray(a).ravel() for a in fields)
+    assert np.max(np.abs(out["n"] - n) / n) < 1e-12
+    assert np.max(np.abs(out["eps"] - eps) / eps) < 1e-12
+    v = out["U"][1:] / out["U"][0]
+    assert np.max(np.abs(v - np.stack([vx, vy, vz]))) < 1e-12
+
+
+def test_conservation_on_device(lat):
+    fields = inputs.random_box(20, 18, 16, 0.5, seed=2)
+    s = rlb.Solver(20, 18, 16, precision="fp64", eta_s=0.2)
+    s.init_fields(*fields)
+    c0 = s.conserved()
+    o = orlb.Solver(20, 18, 16, lat=lat, eta_s=0.2)
+    o.init_fields(*fields)
+    assert np.max(np.abs(c0 - o.conserved())) < 1e-13 * abs(c0[1])
+    s.step(100)
+    c1 = s.conserved()
+    note("conservation drift %s" % ((c1 - c0) / c0[1]))
+    assert np.max(np.abs(c1 - c0)) < 1e-13 * abs(c0[1])
+
+
+def test_uniform_boosted_state_stays(lat):
+    C = 9 * 8 * 7
+    s = rlb.Solver(9, 8, 7, precision="fp64", eta_s=0.3)
+    full = [np.full(C, x) for x in (1.2, 3 * 1.2 * 0.95, 0.3, -0.2, 0.4)]
+    s.init_fields(*full)
+    s.step(20)
+    out = s.read_fields()
+    assert np.max(np.abs(out["n"] - 1.2)) < 1e-13
+    assert np.max(np.abs(out["U"][1] / out["U"][0] - 0.3)) < 1e-13
+
+
+def test_host_init_rejects_nonphysical():
+    s = rlb.Solver(4, 4, 4, precision="fp64", tau=1.0)
+    n, eps, vx, vy, vz = inputs.random_box(4, 4, 4, 0.3, seed=1)
+    vx = vx.copy()
+    vx.flat[5] = 1.0
+    with pytest.raises(rlb.RLBError) as e:
+        s.init_fields(n, eps, vx, vy, vz)
+    assert e.value.code == rlb.ENONPHYS
+    eps = eps.copy()
+    eps.flat[0] = np.nan
+    with pytest.raises(rlb.RLBError):
+        s.init_fields(n, eps, vx * 0, vy, vz)
+    with pytest.raises(rlb.RLBError) as e:
+        s.step(1)
+    assert e.value.code == rlb.ESTATE
+
+
+def test_device_init_flags_nonphysical():
+    import torch
+    s = rlb.Solver(6, 5, 4, precision="fp64", tau=1.0)
+    fields = [torch.tensor(np.asarray(a).ravel(), device="cuda") for a in inputs.random_box(6, 5, 4, 0.3, 1)]
+    fields[0][7] = -1.0
+    s.init_fields(*fields)
+    flags, _ = s.status()
+    assert flags & rlb.FLAG_NONPHYSICAL
+
+
+def test_checkpoint_roundtrip(lat, tmp_path):
+    fields = inputs.random_box(12, 10, 9, 0.5, seed=4)
+    a = rlb.Solver(12, 10, 9, precision="fp64", eta_s=0.1)
+    a.init_fields(*fields)
+    a.step(10)
+    b = rlb.Solver(12, 10, 9, precision="fp64", eta_s=0.1)
+    b.init_fields(*fields)
+    b.step(5)
+    b.save(tmp_path / "ck.bin")
+    c = rlb.Solver(12, 10, 9, precision="fp64", eta_s=0.1)
+    c.load(tmp_path / "ck.bin")
+    c.step(5)
+    ra, rc = a.read_fields(), c.read_fields()
+    for k in ("n", "eps", "U", "P"):
+        assert np.array_equal(ra[k], rc[k])
+    assert c.status()[1] == 10

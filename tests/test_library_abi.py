@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports what include/rlb.h declares; host-only
+calls (no device work) behave as documented.  Runs without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1301_3423_amd import rlb
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(REPO, "include", "rlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(rlb.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = rlb.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_lattice_info_matches_table(lat):
+    info = rlb.lattice_info()
+    assert info["q"] == lat.Q == 128 and info["r2"] == 41 and info["nshell"] == 4
+    assert np.array_equal(info["theta"], lat.theta)
+    assert np.array_equal(info["p0"], lat.p0)
+    assert np.array_equal(info["w"], lat.w)
+    assert np.array_equal(info["inv"], lat.inv)
+    assert np.array_equal(info["shell"], lat.shell)
+    import hashlib
+    path = os.path.join(REPO, "paper_1301_3423_amd", "lattice", "d3q128.txt")
+    assert info["sha256"] == hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def test_state_bytes():
+    b64 = rlb.state_bytes(16, 16, 16, "fp64")
+    b32 = rlb.state_bytes(16, 16, 16, "mixed")
+    cells = 16 ** 3
+    assert b64 >= 2 * 128 * cells * 8 and b32 >= 2 * 128 * cells * 4
+    assert b64 - 2 * 128 * cells * 8 < 2 * 128 * 64 * 8 + 8192
+    assert rlb.state_bytes(0, 4, 4) == 0
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 7) == 0
+
+
+def test_strerror_names_codes():
+    L = rlb.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.rlb_strerror(code).decode() != "unknown error"
+    assert L.rlb_strerror(-99).decode() == "unknown error"
+
+
+def test_create_rejects_bad_arguments():
+    import ctypes
+    L = rlb.lib()
+    h = ctypes.c_void_p()
+    cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_FIXED, 0.4, 0.0)      # tau <= 1/2
+    fake = ctypes.c_void_p(1 << 20)                                    # never dereferenced
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_FIXED, 1.0, 0.0)
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1024, None) == rlb.ENOMEM
+    assert b"needs" in L.rlb_last_error()
+    cfg = rlb.Config(8, 8, 8, 5, rlb.TAU_FIXED, 1.0, 0.0)
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_ETA_S, 0.0, -1.0)
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    assert L.rlb_step(None, 1) == rlb.EINVAL
