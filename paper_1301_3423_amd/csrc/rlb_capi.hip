@@ -46,8 +46,9 @@ int64_t pop_stride(int64_t cells, int precision) {
 bool valid_dims(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   const int64_t c = static_cast<int64_t>(nx) * ny * nz;
-  // byte offsets inside one population array are 32-bit in the kernels
-  return c <= (int64_t(1) << 28);
+  // the kernels address (member offset + cell) * 8 bytes with 32-bit
+  // unsigned offsets: (stride + cells) * 8 < 2^32 for cells <= 2^27
+  return c <= (int64_t(1) << 27);
 }
 
 } // namespace
@@ -93,7 +94,8 @@ unsigned grid_of(int64_t cells) { return static_cast<unsigned>((cells + rlb::BLO
 int launch_step(rlb_solver *s) {
   const rlb::Geom g = geom_of(s);
   const rlb::Relax r = relax_of(s);
-  const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
+  const dim3 grid(static_cast<unsigned>((s->cells + rlb::CELLS_PER_BLOCK - 1) / rlb::CELLS_PER_BLOCK)),
+      block(rlb::BLOCK);
   if (s->cfg.precision == RLB_FP64)
     hipLaunchKernelGGL(rlb::k_step<double>, grid, block, 0, s->stream,
                        static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r,

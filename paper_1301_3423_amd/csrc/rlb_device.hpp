@@ -269,54 +269,73 @@ __device__ __forceinline__ double relaxation_time(const Relax &r, double n, doub
 // Coefficients c of the projected Maxwell-Juttner distribution in the
 // monomial basis: c = G^-1 M, with M the moments of the continuous
 // distribution (Z = n/(2T), N = nU, T = nT(4UU - eta),
-// P = 4nT^2(6UUU - eta U - eta U - eta U)) of each monomial.
+// P = 4nT^2(6UUU - eta U - eta U - eta U)) of each monomial.  G^-1 is block
+// diagonal by the parity class of the monomials, so M is formed one block
+// at a time (at most eight values live).
 struct EqCoef {
   double c[30];
 };
 
+inline constexpr int CLASS_BEGIN[9] = {0, 8, 13, 18, 23, 25, 27, 29, 30};
+
+struct MJ {
+  double n, a, b, U0, Ux, Uy, Uz, Z; // a = nT, b = 4 n T^2, Z = n/(2T)
+  template <int IDX>
+  __device__ __forceinline__ double moment() const {
+    if constexpr (IDX == 0) return Z;
+    else if constexpr (IDX == 1) return n * U0;
+    else if constexpr (IDX == 2) return a * (4.0 * U0 * U0 - 1.0);
+    else if constexpr (IDX == 3) return b * U0 * (6.0 * U0 * U0 - 3.0);
+    else if constexpr (IDX == 4) return a * (4.0 * Ux * Ux + 1.0);
+    else if constexpr (IDX == 5) return a * (4.0 * Uy * Uy + 1.0);
+    else if constexpr (IDX == 6) return b * U0 * (6.0 * Ux * Ux + 1.0);
+    else if constexpr (IDX == 7) return b * U0 * (6.0 * Uy * Uy + 1.0);
+    else if constexpr (IDX == 8) return n * Ux;
+    else if constexpr (IDX == 9) return 4.0 * a * U0 * Ux;
+    else if constexpr (IDX == 10) return b * Ux * (6.0 * U0 * U0 - 1.0);
+    else if constexpr (IDX == 11) return b * Ux * (6.0 * Ux * Ux + 3.0);
+    else if constexpr (IDX == 12) return b * Ux * (6.0 * Uy * Uy + 1.0);
+    else if constexpr (IDX == 13) return n * Uy;
+    else if constexpr (IDX == 14) return 4.0 * a * U0 * Uy;
+    else if constexpr (IDX == 15) return b * Uy * (6.0 * U0 * U0 - 1.0);
+    else if constexpr (IDX == 16) return b * Uy * (6.0 * Ux * Ux + 1.0);
+    else if constexpr (IDX == 17) return b * Uy * (6.0 * Uy * Uy + 3.0);
+    else if constexpr (IDX == 18) return n * Uz;
+    else if constexpr (IDX == 19) return 4.0 * a * U0 * Uz;
+    else if constexpr (IDX == 20) return b * Uz * (6.0 * U0 * U0 - 1.0);
+    else if constexpr (IDX == 21) return b * Uz * (6.0 * Ux * Ux + 1.0);
+    else if constexpr (IDX == 22) return b * Uz * (6.0 * Uy * Uy + 1.0);
+    else if constexpr (IDX == 23) return 4.0 * a * Ux * Uy;
+    else if constexpr (IDX == 24) return 6.0 * b * U0 * Ux * Uy;
+    else if constexpr (IDX == 25) return 4.0 * a * Ux * Uz;
+    else if constexpr (IDX == 26) return 6.0 * b * U0 * Ux * Uz;
+    else if constexpr (IDX == 27) return 4.0 * a * Uy * Uz;
+    else if constexpr (IDX == 28) return 6.0 * b * U0 * Uy * Uz;
+    else return 6.0 * b * Ux * Uy * Uz;
+  }
+};
+
 __device__ __forceinline__ EqCoef eq_coefficients(double n, double T, double U0, double Ux, double Uy,
                                                   double Uz) {
-  const double a = n * T, b = 4.0 * n * T * T;
-  double M[30];
-  M[0] = n / (2.0 * T);
-  M[1] = n * U0;
-  M[2] = a * (4.0 * U0 * U0 - 1.0);
-  M[3] = b * U0 * (6.0 * U0 * U0 - 3.0);
-  M[4] = a * (4.0 * Ux * Ux + 1.0);
-  M[5] = a * (4.0 * Uy * Uy + 1.0);
-  M[6] = b * U0 * (6.0 * Ux * Ux + 1.0);
-  M[7] = b * U0 * (6.0 * Uy * Uy + 1.0);
-  M[8] = n * Ux;
-  M[9] = 4.0 * a * U0 * Ux;
-  M[10] = b * Ux * (6.0 * U0 * U0 - 1.0);
-  M[11] = b * Ux * (6.0 * Ux * Ux + 3.0);
-  M[12] = b * Ux * (6.0 * Uy * Uy + 1.0);
-  M[13] = n * Uy;
-  M[14] = 4.0 * a * U0 * Uy;
-  M[15] = b * Uy * (6.0 * U0 * U0 - 1.0);
-  M[16] = b * Uy * (6.0 * Ux * Ux + 1.0);
-  M[17] = b * Uy * (6.0 * Uy * Uy + 3.0);
-  M[18] = n * Uz;
-  M[19] = 4.0 * a * U0 * Uz;
-  M[20] = b * Uz * (6.0 * U0 * U0 - 1.0);
-  M[21] = b * Uz * (6.0 * Ux * Ux + 1.0);
-  M[22] = b * Uz * (6.0 * Uy * Uy + 1.0);
-  M[23] = 4.0 * a * Ux * Uy;
-  M[24] = 6.0 * b * U0 * Ux * Uy;
-  M[25] = 4.0 * a * Ux * Uz;
-  M[26] = 6.0 * b * U0 * Ux * Uz;
-  M[27] = 4.0 * a * Uy * Uz;
-  M[28] = 6.0 * b * U0 * Uy * Uz;
-  M[29] = 6.0 * b * Ux * Uy * Uz;
+  const MJ mj{n, n * T, 4.0 * n * T * T, U0, Ux, Uy, Uz, n / (2.0 * T)};
   EqCoef e;
-  static_for<0, 30>([&](auto A) {
-    constexpr int ia = decltype(A)::value;
-    double acc = 0.0;
-    static_for<0, 30>([&](auto B) {
-      constexpr int ib = decltype(B)::value;
-      if constexpr (GINV[ia][ib] != 0.0) acc = __builtin_fma(GINV[ia][ib], M[ib], acc);
+  static_for<0, 8>([&](auto B) {
+    constexpr int blk = decltype(B)::value;
+    constexpr int b0 = CLASS_BEGIN[blk], b1 = CLASS_BEGIN[blk + 1];
+    double M[b1 - b0];
+    static_for<b0, b1>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      M[j - b0] = mj.template moment<j>();
     });
-    e.c[ia] = acc;
+    static_for<b0, b1>([&](auto A) {
+      constexpr int ia = decltype(A)::value;
+      double acc = 0.0;
+      static_for<b0, b1>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if constexpr (GINV[ia][j] != 0.0) acc = __builtin_fma(GINV[ia][j], M[j - b0], acc);
+      });
+      e.c[ia] = acc;
+    });
   });
   return e;
 }

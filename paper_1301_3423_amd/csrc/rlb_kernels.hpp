@@ -79,27 +79,162 @@ __device__ __forceinline__ void relax_cell(const S (&f)[Q], const Frame &fr, dou
   });
 }
 
-// One time step: gather, moments, Landau frame, tau, equilibrium,
-// relaxation, aligned store of the post-collision values.
+// ---- the time step: one cell on two lanes ---------------------------------
+//
+// Lanes c and c + 32 of a wavefront share cell c of the wave's 32 cells:
+// the lane with member m = 0 holds point 2k of every inversion pair k, the
+// lane with m = 1 holds point 2k + 1, whose displacement, odd monomials and
+// relaxation asymmetry are those of point 2k with the sign
+// sigma = 1 - 2m.  Each lane therefore runs the same instruction stream
+// with the same immediates: sigma enters once, in the gather offsets, the
+// odd moments, the odd equilibrium coefficients and the velocity.  The 14
+// moments are summed across the two lanes (identical results in both), and
+// both lanes solve the same Landau problem.
+inline constexpr int CELLS_PER_BLOCK = BLOCK / 2;
+
+// (c - s) mod n for a shift s known only at run time, |s| <= MAXD.
+__device__ __forceinline__ int wrap_rt(int c, int s, int n) {
+  if (n > MAXD) {
+    int t = c - s;
+    t += (t < 0) ? n : 0;
+    t -= (t >= n) ? n : 0;
+    return t;
+  }
+  if (n == 1) return 0;
+  return (c - s + (MAXD + 1) * n) % n;
+}
+
+// Per-lane gather offsets of the member m (sign sigma): offsets for the
+// source cell x - sigma*s along each axis, plus m * stride folded into z.
+struct HalfShifts {
+  int xo[2 * MAXD + 1], yo[2 * MAXD + 1], zo[2 * MAXD + 1];
+  __device__ __forceinline__ HalfShifts(int x, int y, int z, int sigma, int m, const Geom &g) {
+    const int mstride = m * static_cast<int>(g.stride);
+#pragma unroll
+    for (int s = -MAXD; s <= MAXD; ++s) {
+      xo[s + MAXD] = wrap_rt(x, sigma * s, g.nx);
+      yo[s + MAXD] = wrap_rt(y, sigma * s, g.ny) * g.nx;
+      zo[s + MAXD] = wrap_rt(z, sigma * s, g.nz) * (g.nx * g.ny) + mstride;
+    }
+  }
+  template <int TX, int TY, int TZ>
+  __device__ __forceinline__ int back() const {
+    return zo[TZ + MAXD] + yo[TY + MAXD] + xo[TX + MAXD];
+  }
+};
+
+__device__ __forceinline__ double add_partner(double v) { return v + __shfl_xor(v, 32); }
+
 template <class S>
-__global__ void __launch_bounds__(BLOCK) k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g,
-                                                Relax rx, unsigned *__restrict__ status) {
-  const int cell = blockIdx.x * BLOCK + threadIdx.x;
-  if (cell >= g.cells) return;
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int m = lane >> 5;
+  const int sigma = 1 - 2 * m;
+  int cell = blockIdx.x * CELLS_PER_BLOCK + (threadIdx.x >> 6) * 32 + (lane & 31);
+  const bool active = cell < g.cells;
+  if (!active) cell = g.cells - 1; // keeps the partner exchange whole; never stored
   int x, y, z;
   cell_coords(cell, g, x, y, z);
-  const Shifts sh(x, y, z, g);
-  S f[Q];
-  gather(cur, g, sh, f);
-  const Moments m = moments(f);
-  Frame fr;
-  unsigned flags = landau_frame(m, fr);
-  const double tau = relaxation_time(rx, fr.n, fr.T);
-  relax_cell(f, fr, tau, [&](auto I, S v) {
-    constexpr int i = decltype(I)::value;
-    store_at(nxt + i * g.stride, cell, v);
+  S f[NPAIR];
+  {
+    const HalfShifts sh(x, y, z, sigma, m, g);
+    static_for<0, NPAIR>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Point P = D3Q128[2 * k];
+      f[k] = load_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>());
+    });
+  }
+  // moments of this lane's members; odd sums carry theta of point 2k
+  Moments mo{};
+  static_for<0, NSHELL>([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    double sh = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0, dx = 0, dy = 0, dz = 0;
+    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Point P = D3Q128[2 * k];
+      const double v = static_cast<double>(f[k]);
+      sh += v;
+      if constexpr (P.tx != 0) sxx = __builtin_fma(double(P.tx * P.tx), v, sxx);
+      if constexpr (P.ty != 0) syy = __builtin_fma(double(P.ty * P.ty), v, syy);
+      if constexpr (P.tz != 0) szz = __builtin_fma(double(P.tz * P.tz), v, szz);
+      if constexpr (P.tx * P.ty != 0) sxy = __builtin_fma(double(P.tx * P.ty), v, sxy);
+      if constexpr (P.tx * P.tz != 0) sxz = __builtin_fma(double(P.tx * P.tz), v, sxz);
+      if constexpr (P.ty * P.tz != 0) syz = __builtin_fma(double(P.ty * P.tz), v, syz);
+      if constexpr (P.tx != 0) dx = __builtin_fma(double(P.tx), v, dx);
+      if constexpr (P.ty != 0) dy = __builtin_fma(double(P.ty), v, dy);
+      if constexpr (P.tz != 0) dz = __builtin_fma(double(P.tz), v, dz);
+    });
+    constexpr double p = shell_p0(l);
+    constexpr double p1r = p * INV_R, p2 = p * p, p2r = p * p * INV_R, p2r2 = p * p * INV_R2;
+    mo.N0 = __builtin_fma(p, sh, mo.N0);
+    mo.T00 = __builtin_fma(p2, sh, mo.T00);
+    mo.Nx = __builtin_fma(p1r, dx, mo.Nx);
+    mo.Ny = __builtin_fma(p1r, dy, mo.Ny);
+    mo.Nz = __builtin_fma(p1r, dz, mo.Nz);
+    mo.T0x = __builtin_fma(p2r, dx, mo.T0x);
+    mo.T0y = __builtin_fma(p2r, dy, mo.T0y);
+    mo.T0z = __builtin_fma(p2r, dz, mo.T0z);
+    mo.Txx = __builtin_fma(p2r2, sxx, mo.Txx);
+    mo.Tyy = __builtin_fma(p2r2, syy, mo.Tyy);
+    mo.Tzz = __builtin_fma(p2r2, szz, mo.Tzz);
+    mo.Txy = __builtin_fma(p2r2, sxy, mo.Txy);
+    mo.Txz = __builtin_fma(p2r2, sxz, mo.Txz);
+    mo.Tyz = __builtin_fma(p2r2, syz, mo.Tyz);
   });
-  if (flags) atomicOr(status, flags);
+  const double sg = static_cast<double>(sigma);
+  mo.Nx *= sg;
+  mo.Ny *= sg;
+  mo.Nz *= sg;
+  mo.T0x *= sg;
+  mo.T0y *= sg;
+  mo.T0z *= sg;
+  mo.N0 = add_partner(mo.N0);
+  mo.Nx = add_partner(mo.Nx);
+  mo.Ny = add_partner(mo.Ny);
+  mo.Nz = add_partner(mo.Nz);
+  mo.T00 = add_partner(mo.T00);
+  mo.T0x = add_partner(mo.T0x);
+  mo.T0y = add_partner(mo.T0y);
+  mo.T0z = add_partner(mo.T0z);
+  mo.Txx = add_partner(mo.Txx);
+  mo.Tyy = add_partner(mo.Tyy);
+  mo.Tzz = add_partner(mo.Tzz);
+  mo.Txy = add_partner(mo.Txy);
+  mo.Txz = add_partner(mo.Txz);
+  mo.Tyz = add_partner(mo.Tyz);
+  Frame fr;
+  const unsigned flags = landau_frame(mo, fr);
+  const double tau = relaxation_time(rx, fr.n, fr.T);
+  EqCoef e = eq_coefficients(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
+  // odd classes (OEE, EOE, EEO, OOO) change sign for the inverse member
+  static_for<CLASS_BEGIN[1], CLASS_BEGIN[4]>([&](auto A) { e.c[decltype(A)::value] *= sg; });
+  e.c[29] *= sg;
+  using CT = S;
+  const double gdt = fr.U0 / tau;
+  const CT gg = CT(gdt);
+  const double gs = gdt * INV_R * sg;
+  const CT bx = CT(gs * fr.vx), by = CT(gs * fr.vy), bz = CT(gs * fr.vz);
+  const int out_off = m * static_cast<int>(g.stride) + cell; // same for every point of this lane
+  static_for<0, NSHELL>([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    const ShellCoef<CT> s = shell_coefficients<l, CT>(e);
+    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr Point P = D3Q128[2 * k];
+      CT E, O;
+      shell_eval<2 * k, CT>(s, E, O);
+      const CT feq = CT(P.w) * (E + O);
+      CT t = CT(0);
+      if constexpr (P.tx != 0) t = fmadd(CT(P.tx), bx, t);
+      if constexpr (P.ty != 0) t = fmadd(CT(P.ty), by, t);
+      if constexpr (P.tz != 0) t = fmadd(CT(P.tz), bz, t);
+      const CT a = f[k];
+      const CT fs = fmadd(gg - t, feq - a, a);
+      if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
+    });
+  });
+  if (active && flags) atomicOr(status, flags);
 }
 
 // Initial state: local equilibrium of (n, eps, v) in every cell, stored so
