@@ -35,7 +35,24 @@ def parse():
     ap.add_argument("--eta-s", type=float, default=0.5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size: 4 GiB read + 4 GiB
+    written per launch, three launches."""
+    import torch
+    n = 4 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
 
 
 def time_steps(solver, steps, warmup):
@@ -98,6 +115,9 @@ def main():
     import torch
     from paper_1301_3423_amd import inputs
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     edge = args.edge
     print("bench: generating %d^3 fields" % edge, file=sys.stderr, flush=True)
     fields = inputs.random_box(edge, edge, edge, args.vmax, seed=3)

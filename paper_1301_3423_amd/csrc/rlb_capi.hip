@@ -94,16 +94,24 @@ unsigned grid_of(int64_t cells) { return static_cast<unsigned>((cells + rlb::BLO
 int launch_step(rlb_solver *s) {
   const rlb::Geom g = geom_of(s);
   const rlb::Relax r = relax_of(s);
-  const dim3 grid(static_cast<unsigned>((s->cells + rlb::CELLS_PER_BLOCK - 1) / rlb::CELLS_PER_BLOCK)),
-      block(rlb::BLOCK);
-  if (s->cfg.precision == RLB_FP64)
+  if (s->cfg.precision == RLB_FP64) {
+    constexpr int TB = rlb::pair_block<double>;
+    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     hipLaunchKernelGGL(rlb::k_step<double>, grid, block, 0, s->stream,
                        static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r,
                        s->status);
-  else
+  } else if (s->cfg.nx % 64 == 0) {
+    const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
+    hipLaunchKernelGGL(rlb::k_step_row<float>, grid, block, 0, s->stream,
+                       static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r,
+                       s->status);
+  } else {
+    constexpr int TB = rlb::pair_block<float>;
+    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     hipLaunchKernelGGL(rlb::k_step<float>, grid, block, 0, s->stream,
                        static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r,
                        s->status);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_step launch");
   s->cur = 1 - s->cur;

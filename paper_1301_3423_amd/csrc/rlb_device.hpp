@@ -159,6 +159,11 @@ __device__ __forceinline__ Moments moments(const S (&f)[Q]) {
       if constexpr (P.tx != 0) dx = __builtin_fma(double(P.tx), d, dx);
       if constexpr (P.ty != 0) dy = __builtin_fma(double(P.ty), d, dy);
       if constexpr (P.tz != 0) dz = __builtin_fma(double(P.tz), d, dz);
+      // finish this pair before the next: otherwise the even chains are sunk
+      // to the end of the shell and every s stays live (an empty statement
+      // that reads and writes the accumulators; it emits no instruction)
+      asm volatile("" : "+v"(sh), "+v"(sxx), "+v"(syy), "+v"(szz), "+v"(sxy), "+v"(sxz), "+v"(syz), "+v"(dx),
+                   "+v"(dy), "+v"(dz));
     });
     constexpr double p = shell_p0(l);
     constexpr double p1r = p * INV_R, p2 = p * p, p2r = p * p * INV_R, p2r2 = p * p * INV_R2;

@@ -90,7 +90,11 @@ __device__ __forceinline__ void relax_cell(const S (&f)[Q], const Frame &fr, dou
 // odd moments, the odd equilibrium coefficients and the velocity.  The 14
 // moments are summed across the two lanes (identical results in both), and
 // both lanes solve the same Landau problem.
-inline constexpr int CELLS_PER_BLOCK = BLOCK / 2;
+// block sizes of the two-lane step kernels (128 cells per block)
+inline constexpr int BLOCK_PAIR64 = 256;
+inline constexpr int BLOCK_PAIR32 = 256;
+template <class S>
+inline constexpr int pair_block = sizeof(S) == 8 ? BLOCK_PAIR64 : BLOCK_PAIR32;
 
 // (c - s) mod n for a shift s known only at run time, |s| <= MAXD.
 __device__ __forceinline__ int wrap_rt(int c, int s, int n) {
@@ -125,13 +129,34 @@ struct HalfShifts {
 
 __device__ __forceinline__ double add_partner(double v) { return v + __shfl_xor(v, 32); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that every XCD walks one contiguous range of the
+// lattice: neighbouring blocks, which read the same cache lines at the
+// ends of their shifted rows, then share an L2.
+inline constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int xcd = b % NUM_XCD, local = b / NUM_XCD;
+  const int per = nb / NUM_XCD, rem = nb % NUM_XCD;
+  // XCDs [0, rem) own per + 1 blocks, the others per
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Float64 populations of the last shell wait in LDS between the moment sums
+// and the relaxation, which keeps the live registers of the float64 kernel
+// within two waves per SIMD.
+inline constexpr int STASH_SHELL = NSHELL - 1;
+inline constexpr int STASH_N = shell_pair_begin(NSHELL) - shell_pair_begin(STASH_SHELL);
+
 template <class S>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
 k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+  constexpr int TB = pair_block<S>;
   const int lane = threadIdx.x & 63;
   const int m = lane >> 5;
   const int sigma = 1 - 2 * m;
-  int cell = blockIdx.x * CELLS_PER_BLOCK + (threadIdx.x >> 6) * 32 + (lane & 31);
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (lane & 31);
   const bool active = cell < g.cells;
   if (!active) cell = g.cells - 1; // keeps the partner exchange whole; never stored
   int x, y, z;
@@ -182,6 +207,14 @@ k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigne
     mo.Txz = __builtin_fma(p2r2, sxz, mo.Txz);
     mo.Tyz = __builtin_fma(p2r2, syz, mo.Tyz);
   });
+  constexpr bool stash = sizeof(S) == 8;
+  __shared__ S lds[stash ? STASH_N : 1][stash ? TB : 1];
+  if constexpr (stash) {
+    static_for<shell_pair_begin(STASH_SHELL), NPAIR>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      lds[k - shell_pair_begin(STASH_SHELL)][threadIdx.x] = f[k];
+    });
+  }
   const double sg = static_cast<double>(sigma);
   mo.Nx *= sg;
   mo.Ny *= sg;
@@ -229,12 +262,66 @@ k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigne
       if constexpr (P.tx != 0) t = fmadd(CT(P.tx), bx, t);
       if constexpr (P.ty != 0) t = fmadd(CT(P.ty), by, t);
       if constexpr (P.tz != 0) t = fmadd(CT(P.tz), bz, t);
-      const CT a = f[k];
+      CT a;
+      if constexpr (stash && l == STASH_SHELL)
+        a = lds[k - shell_pair_begin(STASH_SHELL)][threadIdx.x];
+      else
+        a = f[k];
       const CT fs = fmadd(gg - t, feq - a, a);
       if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
     });
   });
   if (active && flags) atomicOr(status, flags);
+}
+
+// ---- the time step for rows of 64k cells: one cell per lane ---------------
+//
+// When nx is a multiple of 64 every wavefront covers 64 consecutive cells
+// of one row, so the y and z parts of each displacement are the same for
+// the whole wavefront: they go into the scalar base address of each
+// population array, and the lanes only carry the 13 wrapped x offsets.
+// A lane owns a whole cell and uses the inversion pairs directly
+// (s = f_i + f_inv(i) for the even moments, d = f_i - f_inv(i) for the odd
+// ones, and f^eq = w (E +- O) for the two members).
+template <class S>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int cell = blk * BLOCK + threadIdx.x;
+  if (cell >= g.cells) return; // whole wavefronts only: cells is a multiple of 64
+  const int x = cell % g.nx;
+  const int row = __builtin_amdgcn_readfirstlane(cell / g.nx);
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t nxny = static_cast<int64_t>(g.nx) * g.ny;
+  const int64_t row0 = static_cast<int64_t>(row) * g.nx;
+  int xo[2 * MAXD + 1];
+  int yo[2 * MAXD + 1], zo[2 * MAXD + 1]; // wavefront-uniform
+#pragma unroll
+  for (int sft = -MAXD; sft <= MAXD; ++sft) {
+    xo[sft + MAXD] = wrap_back(x, sft, g.nx);
+    yo[sft + MAXD] = wrap_back(y, sft, g.ny) * g.nx;
+    zo[sft + MAXD] = wrap_back(z, sft, g.nz) * static_cast<int>(nxny);
+  }
+  S f[Q];
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr Point P = D3Q128[i];
+    f[i] = load_at(cur + (i * g.stride + yo[P.ty + MAXD] + zo[P.tz + MAXD]), xo[P.tx + MAXD]);
+  });
+  // keep the phases apart: interleaving them raises the register peak
+  __builtin_amdgcn_sched_barrier(0);
+  const Moments m = moments(f);
+  __builtin_amdgcn_sched_barrier(0);
+  Frame fr;
+  const unsigned flags = landau_frame(m, fr);
+  const double tau = relaxation_time(rx, fr.n, fr.T);
+  __builtin_amdgcn_sched_barrier(0);
+  const int own = static_cast<int>(row0) + x;
+  relax_cell(f, fr, tau, [&](auto I, S v) {
+    constexpr int i = decltype(I)::value;
+    store_at(nxt + i * g.stride, own, v);
+  });
+  if (flags) atomicOr(status, flags);
 }
 
 // Initial state: local equilibrium of (n, eps, v) in every cell, stored so

@@ -26,6 +26,9 @@ CASES = [
     ((9, 1, 17), 0.5, 4, dict(tau=1.3)),         # a degenerate axis of size 1
     ((1, 1, 1), 0.3, 3, dict(tau=0.7)),          # a single cell
     ((40, 36, 33), 0.5, 10, dict(eta_s=0.2)),    # 47520 cells: 186 blocks, ragged tail
+    # rows of a multiple of 64 cells (the one-lane-per-cell float32 kernel)
+    ((64, 3, 5), 0.5, 6, dict(eta_s=0.2)),       # y and z edges below 7: modular wrap
+    ((128, 12, 9), 0.5, 6, dict(tau=0.8)),       # 54 blocks of 256
 ]
 
 
