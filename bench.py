@@ -35,10 +35,31 @@ def parse():
     ap.add_argument("--eta-s", type=float, default=0.5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
     return ap.parse_args()
+
+
+def copy_bandwidth():
+    """GB/s (read + write) of a plain 4 GiB device copy, timed with HIP
+    events: the practical streaming ceiling next to the 8 TB/s peak."""
+    import torch
+    n = 4 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n / (ms * 1e-3) / 1e9
 
 
 def copy_calibration():
@@ -53,6 +74,28 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+
+
+def profiled_traffic(kernel, edge):
+    """Measured HBM bytes per launch of `kernel` at edge^3 from a committed
+    rocprofv3 summary, if that summary was taken of the current sources."""
+    from paper_1301_3423_amd.build import source_digest
+    prof_dir = os.path.join(REPO, "profiles")
+    if not os.path.isdir(prof_dir):
+        return None
+    digest = source_digest()
+    for name in sorted(os.listdir(prof_dir)):
+        if not name.endswith(".txt"):
+            continue
+        kv = {}
+        for line in open(os.path.join(prof_dir, name)):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if (kv.get("kernel") == kernel and kv.get("edge") == str(edge)
+                and kv.get("source_sha256") == digest and "traffic_bytes_per_launch" in kv):
+            return float(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def time_steps(solver, steps, warmup):
@@ -119,6 +162,8 @@ def main():
         copy_calibration()
         return
     edge = args.edge
+    copy_gbs = copy_bandwidth()
+    print("bench: plain copy %.0f GB/s" % copy_gbs, file=sys.stderr, flush=True)
     print("bench: generating %d^3 fields" % edge, file=sys.stderr, flush=True)
     fields = inputs.random_box(edge, edge, edge, args.vmax, seed=3)
     print("bench: mixed precision", file=sys.stderr, flush=True)
@@ -129,6 +174,7 @@ def main():
         fp64 = run_box(edge, "fp64", fields, args.steps, args.warmup, args.eta_s)
         print("bench: fp64 %.1f MLUPS" % fp64["mlups"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.vmax, args.eta_s)
+    mixed_kernel = "k_step_row<float>" if edge % 64 == 0 else "k_step<float>"
     line = {
         "metric": "MLUPS at 256^3 FP64 vs FP32-mixed (% HBM roofline); served p50/p99 latency",
         "value": round(mixed["mlups"], 2),
@@ -148,15 +194,20 @@ def main():
                    "cells": edge ** 3, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(mixed["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(mixed["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": profiled_traffic(mixed_kernel, edge),
+                     "kernel": mixed_kernel, "algorithmic_bytes_per_launch": mixed["bytes_per_launch"]},
         "status_flags": mixed["flags"],
+        "copy_GBps": round(copy_gbs, 1),
     }
     if fp64 is not None:
         line["fp64"] = {"value": round(fp64["mlups"], 2), "unit": "MLUPS", "dtype": "f64",
                         "ms_per_step": round(fp64["ms_per_step"], 4),
                         "roofline": {"bound": "hbm", "achieved": round(fp64["achieved_gbs"], 1),
                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": round(fp64["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None},
+                                     "frac": round(fp64["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                                     "traffic": profiled_traffic("k_step<double>", edge),
+                                     "kernel": "k_step<double>",
+                                     "algorithmic_bytes_per_launch": fp64["bytes_per_launch"]},
                         "status_flags": fp64["flags"],
                         "mixed_over_fp64": round(mixed["mlups"] / fp64["mlups"], 3)}
     if cpu is not None:

@@ -24,6 +24,23 @@ HIP_FLAGS = [
 ]
 
 
+def source_digest():
+    """sha256 over the kernel sources and compiled-in tables: identifies the
+    kernels a profile was taken of."""
+    import hashlib
+    h = hashlib.sha256()
+    files = []
+    for d in (os.path.join(PKG, "csrc"), os.path.join(PKG, "lattice")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".hpp", ".inc", ".sha")):
+                files.append(os.path.join(d, f))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
