@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--eta-s", type=float, default=0.5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tubes", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
     return ap.parse_args()
@@ -130,6 +131,31 @@ def run_box(edge, precision, fields, steps, warmup, eta_s):
     return out
 
 
+def run_tubes(precision, ntubes=512, steps=500, seed=4):
+    """Many independent shock tubes in one persistent launch."""
+    import torch
+    from paper_1301_3423_amd import inputs, rlb
+    spec = inputs.tube_batch(ntubes, seed)
+    tubes = [dict(n=t["N"], eta_s=t["eta_s"]) for t in spec]
+    b = rlb.Batch(tubes, precision=precision)
+    for j, t in enumerate(spec):
+        b.init_tube(j, *inputs.shock_tube(t["N"], t["T_left"], t["T_right"]))
+    b.step(2)                       # warm-up launch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lu = sum(t["N"] for t in spec) * steps
+    flags = [b.status(j)[0] for j in range(len(spec))]
+    bpl = 2 * Q * (8 if precision == "fp64" else 4)
+    return dict(mlups=lu / (ms * 1e-3) / 1e6, ms=ms, cells=sum(t["N"] for t in spec),
+                achieved_gbs=lu * bpl / (ms * 1e-3) / 1e9, tubes_flagged=sum(1 for f in flags if f))
+
+
 def cpu_baseline(vmax, eta_s):
     """The FP64 oracle on a bounded sample of the same workload."""
     from threadpoolctl import threadpool_limits
@@ -173,6 +199,14 @@ def main():
     if not args.no_fp64:
         fp64 = run_box(edge, "fp64", fields, args.steps, args.warmup, args.eta_s)
         print("bench: fp64 %.1f MLUPS" % fp64["mlups"], file=sys.stderr, flush=True)
+    tubes = {}
+    if not args.no_tubes:
+        for prec in ("fp64", "mixed"):
+            r = run_tubes(prec)
+            print("bench: tubes %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
+            tubes[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "launch_ms": round(r["ms"], 3),
+                           "achieved_GBps": round(r["achieved_gbs"], 1), "cells": r["cells"],
+                           "tubes_flagged": r["tubes_flagged"]}
     cpu = None if args.no_cpu else cpu_baseline(args.vmax, args.eta_s)
     mixed_kernel = "k_step_row<float>" if edge % 64 == 0 else "k_step<float>"
     line = {
@@ -210,6 +244,10 @@ def main():
                                      "algorithmic_bytes_per_launch": fp64["bytes_per_launch"]},
                         "status_flags": fp64["flags"],
                         "mixed_over_fp64": round(mixed["mlups"] / fp64["mlups"], 3)}
+    if tubes:
+        line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
+                                     "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",
+                         **tubes}
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -166,6 +166,52 @@ int rlb_load(rlb_solver *s, const char *path);
 /* Releases the solver's host allocations (not the caller's buffer). */
 void rlb_destroy(rlb_solver *s);
 
+/* ---- many independent shock tubes (1 x 1 x n periodic lattices) ------------
+ * The Riemann problems of Sec. III are one-dimensional: a tube is a periodic
+ * 1 x 1 x n lattice on which only the z displacement of each point moves
+ * anything.  A batch holds many tubes of one precision in one caller-owned
+ * buffer and advances all of them in one persistent launch: one workgroup
+ * per tube, each looping over that tube's steps with a workgroup barrier
+ * between steps, launched longest-work-first.  Tubes never interact; a
+ * failure (status flag) stays in its tube. */
+typedef struct rlb_tube {
+  int32_t n;        /* cells along z, >= 1                                  */
+  int32_t tau_mode; /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */
+  double tau;       /* when tau_mode == RLB_TAU_FIXED (> 1/2)               */
+  double eta_s;     /* when tau_mode == RLB_TAU_ETA_S (> 0)                 */
+} rlb_tube;
+
+typedef struct rlb_batch rlb_batch;
+
+/* Device bytes for a batch of these tubes (0 if any tube is invalid). */
+size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision);
+
+/* Creates a batch over caller-owned device memory (>= rlb_batch_bytes,
+ * 256-byte aligned) on `stream`.  The tube array is copied.  Errors as for
+ * rlb_create. */
+int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, void *d_buf,
+                     size_t bytes, void *stream);
+
+/* Initial fields of one tube (n values each, index = z); semantics and
+ * errors as rlb_init_fields.  Resets that tube's t and flags. */
+int rlb_batch_init(rlb_batch *b, int32_t tube, const double *n, const double *eps, const double *vx,
+                   const double *vy, const double *vz, int32_t on_device);
+
+/* One persistent launch: tube j advances steps[j] >= 0 steps (0 leaves it
+ * untouched).  Every tube with steps[j] > 0 must have been initialised.
+ * Asynchronous on the batch's stream. */
+int rlb_batch_step(rlb_batch *b, const int64_t *steps);
+
+/* Fields of one tube, as rlb_read_fields (U4 holds 4 n values). */
+int rlb_batch_read(rlb_batch *b, int32_t tube, double *n, double *eps, double *U4, double *P,
+                   int32_t on_device);
+
+/* Status flags and step count of one tube (synchronises the stream). */
+int rlb_batch_status(rlb_batch *b, int32_t tube, uint32_t *flags, int64_t *t);
+
+/* Releases the batch's host allocations. */
+void rlb_batch_destroy(rlb_batch *b);
+
 /* ---- diagnostics --------------------------------------------------------- */
 const char *rlb_strerror(int code);
 const char *rlb_last_error(void);

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -412,6 +413,304 @@ int rlb_load(rlb_solver *s, const char *path) {
   s->t = h.t;
   s->initialized = true;
   return RLB_OK;
+}
+
+// ---- batches of shock tubes -------------------------------------------------
+
+} // extern "C"
+
+struct rlb_batch {
+  int precision;
+  int device;
+  hipStream_t stream;
+  char *base;
+  size_t bytes;
+  int ntubes;
+  std::vector<rlb_tube> tubes;
+  std::vector<rlb::TubeDesc> desc; // host view (cur, steps updated per launch)
+  std::vector<int64_t> t;
+  std::vector<char> initialized;
+  rlb::TubeDesc *d_desc;
+  int *d_order;
+  unsigned *d_status;
+  char *pops; // population area
+  // pinned staging for descriptors and order, guarded by an event
+  rlb::TubeDesc *h_desc;
+  int *h_order;
+  hipEvent_t staged;
+  bool staged_pending;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+bool valid_tube(const rlb_tube &tb) {
+  if (tb.n < 1 || tb.n > (1 << 27)) return false;
+  if (tb.tau_mode == RLB_TAU_FIXED) return tb.tau > 0.5 && std::isfinite(tb.tau);
+  if (tb.tau_mode == RLB_TAU_ETA_S) return tb.eta_s > 0.0 && std::isfinite(tb.eta_s);
+  return false;
+}
+
+size_t batch_header_bytes(int ntubes) {
+  return align256(ntubes * sizeof(rlb::TubeDesc)) + align256(ntubes * sizeof(int)) +
+         align256(ntubes * sizeof(unsigned));
+}
+
+size_t tube_buffer_bytes(int32_t n, int precision) {
+  return align256(static_cast<size_t>(rlb::Q) * pop_stride(n, precision) * elem_bytes(precision));
+}
+
+rlb::Geom tube_geom(const rlb_batch *b, int j) {
+  rlb::Geom g;
+  g.nx = 1;
+  g.ny = 1;
+  g.nz = b->tubes[j].n;
+  g.cells = b->tubes[j].n;
+  g.stride = b->desc[j].stride;
+  return g;
+}
+
+void *tube_buf(rlb_batch *b, int j, int which) {
+  const size_t eb = elem_bytes(b->precision);
+  return b->pops - 0 + static_cast<size_t>(b->desc[j].off[which]) * eb;
+}
+
+int wait_staged(rlb_batch *b) {
+  if (b->staged_pending) {
+    RLB_HIP(hipEventSynchronize(b->staged));
+    b->staged_pending = false;
+  }
+  return RLB_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision) {
+  if (!tubes || ntubes < 1 || (precision != RLB_FP64 && precision != RLB_MIXED)) return 0;
+  size_t total = batch_header_bytes(ntubes);
+  for (int j = 0; j < ntubes; ++j) {
+    if (!valid_tube(tubes[j])) return 0;
+    total += 2 * tube_buffer_bytes(tubes[j].n, precision);
+  }
+  return total;
+}
+
+int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, void *d_buf,
+                     size_t bytes, void *stream) {
+  if (!out || !tubes || !d_buf) return fail(RLB_EINVAL, "rlb_batch_create: NULL argument");
+  *out = nullptr;
+  if (ntubes < 1) return fail(RLB_EINVAL, "rlb_batch_create: no tubes");
+  if (precision != RLB_FP64 && precision != RLB_MIXED) return fail(RLB_EINVAL, "rlb_batch_create: bad precision");
+  for (int j = 0; j < ntubes; ++j)
+    if (!valid_tube(tubes[j])) return fail(RLB_EINVAL, "rlb_batch_create: tube " + std::to_string(j) + " is invalid");
+  if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_batch_create: buffer not 256-byte aligned");
+  const size_t need = rlb_batch_bytes(tubes, ntubes, precision);
+  if (bytes < need)
+    return fail(RLB_ENOMEM, "rlb_batch_create: buffer has " + std::to_string(bytes) + " bytes, needs " + std::to_string(need));
+  int dev = 0;
+  RLB_HIP(hipGetDevice(&dev));
+  rlb_batch *b = new (std::nothrow) rlb_batch();
+  if (!b) return fail(RLB_EINVAL, "rlb_batch_create: out of host memory");
+  b->precision = precision;
+  b->device = dev;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->base = static_cast<char *>(d_buf);
+  b->bytes = bytes;
+  b->ntubes = ntubes;
+  b->tubes.assign(tubes, tubes + ntubes);
+  b->desc.resize(ntubes);
+  b->t.assign(ntubes, 0);
+  b->initialized.assign(ntubes, 0);
+  char *p = b->base;
+  b->d_desc = reinterpret_cast<rlb::TubeDesc *>(p);
+  p += align256(ntubes * sizeof(rlb::TubeDesc));
+  b->d_order = reinterpret_cast<int *>(p);
+  p += align256(ntubes * sizeof(int));
+  b->d_status = reinterpret_cast<unsigned *>(p);
+  p += align256(ntubes * sizeof(unsigned));
+  b->pops = p;
+  const size_t eb = elem_bytes(precision);
+  size_t off = 0; // bytes from pops
+  for (int j = 0; j < ntubes; ++j) {
+    rlb::TubeDesc &d = b->desc[j];
+    const size_t tb = tube_buffer_bytes(tubes[j].n, precision);
+    d.off[0] = static_cast<int64_t>(off / eb);
+    d.off[1] = static_cast<int64_t>((off + tb) / eb);
+    off += 2 * tb;
+    d.steps = 0;
+    d.n = tubes[j].n;
+    d.stride = static_cast<int32_t>(pop_stride(tubes[j].n, precision));
+    d.cur = 0;
+    d.mode = tubes[j].tau_mode == RLB_TAU_ETA_S ? 1 : 0;
+    d.tau = tubes[j].tau;
+    d.eta_s = tubes[j].eta_s;
+  }
+  b->h_desc = nullptr;
+  b->h_order = nullptr;
+  b->staged_pending = false;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&b->h_desc), ntubes * sizeof(rlb::TubeDesc), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&b->h_order), ntubes * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->h_order) (void)hipHostFree(b->h_order);
+    delete b;
+    return hip_fail(e, "rlb_batch_create: pinned staging");
+  }
+  e = hipMemsetAsync(b->d_status, 0, ntubes * sizeof(unsigned), b->stream);
+  if (e != hipSuccess) {
+    rlb_batch_destroy(b);
+    return hip_fail(e, "rlb_batch_create: status clear");
+  }
+  *out = b;
+  return RLB_OK;
+}
+
+int rlb_batch_init(rlb_batch *b, int32_t tube, const double *n, const double *eps, const double *vx,
+                   const double *vy, const double *vz, int32_t on_device) {
+  if (!b || !n || !eps || !vx || !vy || !vz) return fail(RLB_EINVAL, "rlb_batch_init: NULL argument");
+  if (tube < 0 || tube >= b->ntubes) return fail(RLB_EINVAL, "rlb_batch_init: tube index out of range");
+  const int64_t C = b->tubes[tube].n;
+  const int cur = b->desc[tube].cur;
+  const double *dn = n, *de = eps, *dx = vx, *dy = vy, *dz = vz;
+  double *stage = static_cast<double *>(tube_buf(b, tube, 1 - cur));
+  if (!on_device) {
+    const double *arrs[5] = {n, eps, vx, vy, vz};
+    for (auto a : arrs)
+      if (!finite_all(a, C)) return fail(RLB_ENONPHYS, "rlb_batch_init: non-finite value");
+    for (int64_t c = 0; c < C; ++c) {
+      const double v2 = vx[c] * vx[c] + vy[c] * vy[c] + vz[c] * vz[c];
+      if (!(n[c] > 0.0) || !(eps[c] > 0.0) || !(v2 < 1.0))
+        return fail(RLB_ENONPHYS, "rlb_batch_init: cell " + std::to_string(c) + " has n<=0, eps<=0 or |v|>=1");
+    }
+    for (int k = 0; k < 5; ++k)
+      RLB_HIP(hipMemcpyAsync(stage + k * C, arrs[k], C * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    dn = stage;
+    de = stage + C;
+    dx = stage + 2 * C;
+    dy = stage + 3 * C;
+    dz = stage + 4 * C;
+  }
+  RLB_HIP(hipMemsetAsync(b->d_status + tube, 0, sizeof(unsigned), b->stream));
+  const rlb::Geom g = tube_geom(b, tube);
+  const dim3 grid(grid_of(C)), block(rlb::BLOCK);
+  if (b->precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_init<double>, grid, block, 0, b->stream, dn, de, dx, dy, dz,
+                       static_cast<double *>(tube_buf(b, tube, cur)), g, b->d_status + tube);
+  else
+    hipLaunchKernelGGL(rlb::k_init<float>, grid, block, 0, b->stream, dn, de, dx, dy, dz,
+                       static_cast<float *>(tube_buf(b, tube, cur)), g, b->d_status + tube);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_init launch");
+  if (!on_device) RLB_HIP(hipStreamSynchronize(b->stream));
+  b->t[tube] = 0;
+  b->initialized[tube] = 1;
+  return RLB_OK;
+}
+
+int rlb_batch_step(rlb_batch *b, const int64_t *steps) {
+  if (!b || !steps) return fail(RLB_EINVAL, "rlb_batch_step: NULL argument");
+  int active = 0;
+  for (int j = 0; j < b->ntubes; ++j) {
+    if (steps[j] < 0) return fail(RLB_EINVAL, "rlb_batch_step: negative step count for tube " + std::to_string(j));
+    if (steps[j] > 0 && !b->initialized[j])
+      return fail(RLB_ESTATE, "rlb_batch_step: tube " + std::to_string(j) + " is not initialised");
+    if (steps[j] > 0) ++active;
+  }
+  if (active == 0) return RLB_OK;
+  int rc = wait_staged(b);
+  if (rc != RLB_OK) return rc;
+  // longest work first (cells x steps), ties by index
+  std::vector<int> order;
+  order.reserve(active);
+  for (int j = 0; j < b->ntubes; ++j)
+    if (steps[j] > 0) order.push_back(j);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return static_cast<double>(b->tubes[a].n) * steps[a] > static_cast<double>(b->tubes[c].n) * steps[c];
+  });
+  for (int j = 0; j < b->ntubes; ++j) {
+    b->desc[j].steps = steps[j];
+    b->h_desc[j] = b->desc[j];
+  }
+  for (int k = 0; k < active; ++k) b->h_order[k] = order[k];
+  RLB_HIP(hipMemcpyAsync(b->d_desc, b->h_desc, b->ntubes * sizeof(rlb::TubeDesc), hipMemcpyHostToDevice, b->stream));
+  RLB_HIP(hipMemcpyAsync(b->d_order, b->h_order, active * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  RLB_HIP(hipEventRecord(b->staged, b->stream));
+  b->staged_pending = true;
+  const dim3 grid(active);
+  if (b->precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_tubes<double>, grid, dim3(rlb::TUBE_BLOCK), 0, b->stream,
+                       reinterpret_cast<double *>(b->pops), b->d_desc, b->d_order, b->d_status);
+  else
+    hipLaunchKernelGGL(rlb::k_tubes<float>, grid, dim3(rlb::TUBE_BLOCK), 0, b->stream,
+                       reinterpret_cast<float *>(b->pops), b->d_desc, b->d_order, b->d_status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_tubes launch");
+  for (int j = 0; j < b->ntubes; ++j) {
+    b->desc[j].cur ^= static_cast<int32_t>(steps[j] & 1);
+    b->desc[j].steps = 0;
+    b->t[j] += steps[j];
+  }
+  return RLB_OK;
+}
+
+int rlb_batch_read(rlb_batch *b, int32_t tube, double *n, double *eps, double *U4, double *P, int32_t on_device) {
+  if (!b) return fail(RLB_EINVAL, "rlb_batch_read: NULL batch");
+  if (tube < 0 || tube >= b->ntubes) return fail(RLB_EINVAL, "rlb_batch_read: tube index out of range");
+  if (!b->initialized[tube]) return fail(RLB_ESTATE, "rlb_batch_read: tube is not initialised");
+  const int64_t C = b->tubes[tube].n;
+  const int cur = b->desc[tube].cur;
+  double *dn = n, *de = eps, *dU = U4, *dP = P;
+  double *stage = static_cast<double *>(tube_buf(b, tube, 1 - cur));
+  if (!on_device) {
+    dn = n ? stage : nullptr;
+    de = eps ? stage + C : nullptr;
+    dU = U4 ? stage + 2 * C : nullptr;
+    dP = P ? stage + 6 * C : nullptr;
+  }
+  const rlb::Geom g = tube_geom(b, tube);
+  const dim3 grid(grid_of(C)), block(rlb::BLOCK);
+  if (b->precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_read<double>, grid, block, 0, b->stream,
+                       static_cast<const double *>(tube_buf(b, tube, cur)), g, dn, de, dU, dP, b->d_status + tube);
+  else
+    hipLaunchKernelGGL(rlb::k_read<float>, grid, block, 0, b->stream,
+                       static_cast<const float *>(tube_buf(b, tube, cur)), g, dn, de, dU, dP, b->d_status + tube);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_read launch");
+  if (!on_device) {
+    if (n) RLB_HIP(hipMemcpyAsync(n, dn, C * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (eps) RLB_HIP(hipMemcpyAsync(eps, de, C * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (U4) RLB_HIP(hipMemcpyAsync(U4, dU, 4 * C * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if (P) RLB_HIP(hipMemcpyAsync(P, dP, C * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    RLB_HIP(hipStreamSynchronize(b->stream));
+  }
+  return RLB_OK;
+}
+
+int rlb_batch_status(rlb_batch *b, int32_t tube, uint32_t *flags, int64_t *t) {
+  if (!b) return fail(RLB_EINVAL, "rlb_batch_status: NULL batch");
+  if (tube < 0 || tube >= b->ntubes) return fail(RLB_EINVAL, "rlb_batch_status: tube index out of range");
+  if (flags) {
+    unsigned h = 0;
+    RLB_HIP(hipMemcpyAsync(&h, b->d_status + tube, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream));
+    RLB_HIP(hipStreamSynchronize(b->stream));
+    *flags = h;
+  }
+  if (t) *t = b->t[tube];
+  return RLB_OK;
+}
+
+void rlb_batch_destroy(rlb_batch *b) {
+  if (!b) return;
+  if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+  (void)hipEventDestroy(b->staged);
+  if (b->h_desc) (void)hipHostFree(b->h_desc);
+  if (b->h_order) (void)hipHostFree(b->h_order);
+  delete b;
 }
 
 void rlb_destroy(rlb_solver *s) { delete s; }

@@ -142,21 +142,22 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Float64 populations of the last shell wait in LDS between the moment sums
-// and the relaxation, which keeps the live registers of the float64 kernel
-// within two waves per SIMD.
-inline constexpr int STASH_SHELL = NSHELL - 1;
-inline constexpr int STASH_N = shell_pair_begin(NSHELL) - shell_pair_begin(STASH_SHELL);
+// Float64 populations of the last STASH_N pairs wait in LDS between the
+// moment sums and the relaxation (64 KB per 256-thread block), which keeps
+// the live registers of the float64 kernels within two waves per SIMD.
+inline constexpr int STASH_N = 32;
+inline constexpr int STASH_BEGIN = NPAIR - STASH_N;
 
-template <class S>
-__global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
-k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
-  constexpr int TB = pair_block<S>;
+// One lattice update of `cell` by the two lanes (c, c + 32) of a wavefront
+// (see above); `lds` is the block's stash of the last shell (float64 only,
+// [STASH_N][block size]).  Cells at or beyond g.cells are computed for a
+// clamped cell and never stored.  OR-s this cell's flags into `flags`.
+template <class S, int TB>
+__device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__restrict__ nxt, const Geom &g,
+                                               const Relax &rx, int cell, S (*lds)[TB], unsigned &flags) {
   const int lane = threadIdx.x & 63;
   const int m = lane >> 5;
   const int sigma = 1 - 2 * m;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (lane & 31);
   const bool active = cell < g.cells;
   if (!active) cell = g.cells - 1; // keeps the partner exchange whole; never stored
   int x, y, z;
@@ -208,12 +209,14 @@ k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigne
     mo.Tyz = __builtin_fma(p2r2, syz, mo.Tyz);
   });
   constexpr bool stash = sizeof(S) == 8;
-  __shared__ S lds[stash ? STASH_N : 1][stash ? TB : 1];
   if constexpr (stash) {
-    static_for<shell_pair_begin(STASH_SHELL), NPAIR>([&](auto K) {
+    static_for<STASH_BEGIN, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      lds[k - shell_pair_begin(STASH_SHELL)][threadIdx.x] = f[k];
+      lds[k - STASH_BEGIN][threadIdx.x] = f[k];
     });
+    // compiler-only fence: the values must really be reloaded from LDS
+    // later (forwarding the stores would keep them in registers)
+    asm volatile("" ::: "memory");
   }
   const double sg = static_cast<double>(sigma);
   mo.Nx *= sg;
@@ -237,7 +240,7 @@ k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigne
   mo.Txz = add_partner(mo.Txz);
   mo.Tyz = add_partner(mo.Tyz);
   Frame fr;
-  const unsigned flags = landau_frame(mo, fr);
+  const unsigned fl = landau_frame(mo, fr);
   const double tau = relaxation_time(rx, fr.n, fr.T);
   EqCoef e = eq_coefficients(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
   // odd classes (OEE, EOE, EEO, OOO) change sign for the inverse member
@@ -263,15 +266,116 @@ k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigne
       if constexpr (P.ty != 0) t = fmadd(CT(P.ty), by, t);
       if constexpr (P.tz != 0) t = fmadd(CT(P.tz), bz, t);
       CT a;
-      if constexpr (stash && l == STASH_SHELL)
-        a = lds[k - shell_pair_begin(STASH_SHELL)][threadIdx.x];
+      if constexpr (stash && k >= STASH_BEGIN)
+        a = lds[k - STASH_BEGIN][threadIdx.x];
       else
         a = f[k];
       const CT fs = fmadd(gg - t, feq - a, a);
       if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
     });
   });
-  if (active && flags) atomicOr(status, flags);
+  if (active) flags |= fl;
+}
+
+
+template <class S>
+__global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
+k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+  constexpr int TB = pair_block<S>;
+  constexpr bool stash = sizeof(S) == 8;
+  __shared__ S lds[stash ? STASH_N : 1][TB];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
+  unsigned flags = 0;
+  pair_cell_step<S, TB>(cur, nxt, g, rx, cell, lds, flags);
+  if (flags) atomicOr(status, flags);
+}
+
+// ---- many shock tubes in one persistent launch ----------------------------
+//
+// One workgroup per tube (taken from `order`, longest work first), looping
+// over that tube's steps; each step sweeps the tube in passes of TB/2 cells
+// and ends with a workgroup barrier, which also makes the step's stores
+// visible to the next step's gathers (all waves of a workgroup share one
+// CU and its caches).  Tubes are independent, so no workgroup ever waits on
+// another, and every workgroup leaves after its own step count.
+struct TubeDesc {
+  int64_t off[2]; // element offsets of the tube's two population buffers
+  int64_t steps;  // steps to take in this launch
+  int32_t n;      // cells along z
+  int32_t stride; // elements between consecutive populations
+  int32_t cur;    // buffer holding the current state
+  int32_t mode;   // 0 fixed tau, 1 tau from eta/s
+  double tau, eta_s;
+};
+
+inline constexpr int TUBE_BLOCK = 512; // one workgroup fills a CU at two waves per SIMD
+
+// One tube cell per lane (float32): the cell index is z, so each lane keeps
+// the 13 wrapped z offsets and every population base is wavefront-uniform.
+template <class S>
+__device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__restrict__ out, const Geom &g,
+                                               const Relax &rx, int z, unsigned &flags) {
+  const bool active = z < g.cells;
+  const int zc = active ? z : g.cells - 1;
+  int zo[2 * MAXD + 1];
+#pragma unroll
+  for (int s = -MAXD; s <= MAXD; ++s) zo[s + MAXD] = wrap_back(zc, s, g.nz);
+  S f[Q];
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr Point P = D3Q128[i];
+    f[i] = load_at(in + i * g.stride, zo[P.tz + MAXD]);
+  });
+  const Moments m = moments(f);
+  Frame fr;
+  const unsigned fl = landau_frame(m, fr);
+  const double tau = relaxation_time(rx, fr.n, fr.T);
+  relax_cell(f, fr, tau, [&](auto I, S v) {
+    constexpr int i = decltype(I)::value;
+    if (active) store_at(out + i * g.stride, zc, v);
+  });
+  if (active) flags |= fl;
+}
+
+template <class S>
+__global__ void __launch_bounds__(TUBE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__restrict__ order,
+        unsigned *__restrict__ status) {
+  constexpr bool f64 = sizeof(S) == 8;
+  constexpr int TB = TUBE_BLOCK;
+  __shared__ S lds[f64 ? STASH_N : 1][f64 ? TB : 1];
+  const int j = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
+  const TubeDesc d = desc[j]; // uniform: scalar loads
+  Geom g;
+  g.nx = 1;
+  g.ny = 1;
+  g.nz = d.n;
+  g.cells = d.n;
+  g.stride = d.stride;
+  Relax rx;
+  rx.mode = d.mode;
+  rx.tau = d.tau;
+  rx.eta_s = d.eta_s;
+  // float64: two lanes per cell, TB/2 cells per pass; float32: one lane per
+  // cell, TB cells per pass
+  constexpr int per_pass = f64 ? TB / 2 : TB;
+  const int slot = f64 ? (threadIdx.x >> 6) * 32 + (threadIdx.x & 31) : static_cast<int>(threadIdx.x);
+  unsigned flags = 0;
+  int cur = d.cur;
+  for (int64_t st = 0; st < d.steps; ++st) {
+    const S *in = base + (cur ? d.off[1] : d.off[0]);
+    S *out = base + (cur ? d.off[0] : d.off[1]);
+    for (int c0 = 0; c0 < d.n; c0 += per_pass) {
+      if constexpr (f64)
+        pair_cell_step<S, TB>(in, out, g, rx, c0 + slot, lds, flags);
+      else
+        tube_cell_step<S>(in, out, g, rx, c0 + slot, flags);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (flags) atomicOr(status + j, flags);
 }
 
 // ---- the time step for rows of 64k cells: one cell per lane ---------------

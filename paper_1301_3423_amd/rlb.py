@@ -28,7 +28,8 @@ MAX_Q = 128
 # every symbol include/rlb.h declares
 EXPORTS = ("rlb_lattice_info", "rlb_state_bytes", "rlb_create", "rlb_init_fields", "rlb_step",
            "rlb_read_fields", "rlb_conserved", "rlb_status", "rlb_save", "rlb_load", "rlb_destroy",
-           "rlb_strerror", "rlb_last_error")
+           "rlb_batch_bytes", "rlb_batch_create", "rlb_batch_init", "rlb_batch_step", "rlb_batch_read",
+           "rlb_batch_status", "rlb_batch_destroy", "rlb_strerror", "rlb_last_error")
 
 
 class RLBError(RuntimeError):
@@ -55,6 +56,11 @@ class Config(ctypes.Structure):
                 ("tau", ctypes.c_double), ("eta_s", ctypes.c_double)]
 
 
+class Tube(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("eta_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -79,6 +85,15 @@ def lib():
         L.rlb_load.argtypes = [vp, ctypes.c_char_p]
         L.rlb_destroy.argtypes = [vp]
         L.rlb_destroy.restype = None
+        L.rlb_batch_bytes.argtypes = [ctypes.POINTER(Tube), i32, i32]
+        L.rlb_batch_bytes.restype = ctypes.c_size_t
+        L.rlb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Tube), i32, i32, vp, ctypes.c_size_t, vp]
+        L.rlb_batch_init.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32]
+        L.rlb_batch_step.argtypes = [vp, ctypes.POINTER(i64)]
+        L.rlb_batch_read.argtypes = [vp, i32, vp, vp, vp, vp, i32]
+        L.rlb_batch_status.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64)]
+        L.rlb_batch_destroy.argtypes = [vp]
+        L.rlb_batch_destroy.restype = None
         L.rlb_strerror.argtypes = [ctypes.c_int]
         L.rlb_strerror.restype = ctypes.c_char_p
         L.rlb_last_error.restype = ctypes.c_char_p
@@ -205,3 +220,74 @@ class Solver:
 
     def load(self, path):
         check(lib().rlb_load(self._h, str(path).encode()))
+
+
+def _tube_struct(t):
+    """A tube given as dict(n=..., tau=...) or dict(n=..., eta_s=...)."""
+    if ("tau" in t) == ("eta_s" in t):
+        raise ValueError("a tube needs exactly one of tau, eta_s")
+    if "tau" in t:
+        return Tube(int(t["n"]), TAU_FIXED, float(t["tau"]), 0.0)
+    return Tube(int(t["n"]), TAU_ETA_S, 0.0, float(t["eta_s"]))
+
+
+def batch_bytes(tubes, precision="fp64"):
+    arr = (Tube * len(tubes))(*[_tube_struct(t) for t in tubes])
+    return lib().rlb_batch_bytes(arr, len(tubes), _prec(precision))
+
+
+class Batch:
+    """Many independent 1 x 1 x n shock tubes of one precision, advanced
+    together by one persistent launch per step() call."""
+
+    def __init__(self, tubes, precision="fp64", stream=None, device=None):
+        import torch
+        self.tubes = [dict(t) for t in tubes]
+        self.precision = precision
+        arr = (Tube * len(tubes))(*[_tube_struct(t) for t in tubes])
+        nbytes = lib().rlb_batch_bytes(arr, len(tubes), _prec(precision))
+        if nbytes == 0:
+            raise RLBError(EINVAL, "invalid tube list")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().rlb_batch_create(ctypes.byref(h), arr, len(tubes), _prec(precision),
+                                     ctypes.c_void_p(self.buffer.data_ptr()), nbytes, _stream_ptr(self.stream)))
+        self._h = h
+
+    def __len__(self):
+        return len(self.tubes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rlb_batch_destroy(h)
+            self._h = None
+
+    def init_tube(self, j, n, eps, vx, vy, vz):
+        hs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)).ravel() for a in (n, eps, vx, vy, vz)]
+        for h in hs:
+            if h.size != self.tubes[j]["n"]:
+                raise ValueError("tube %d has %d cells, got %d values" % (j, self.tubes[j]["n"], h.size))
+        check(lib().rlb_batch_init(self._h, int(j), *[ctypes.c_void_p(h.ctypes.data) for h in hs], 0))
+
+    def step(self, steps):
+        """steps: one count for every tube, or a sequence with one per tube."""
+        if np.isscalar(steps):
+            steps = [int(steps)] * len(self.tubes)
+        arr = (ctypes.c_int64 * len(self.tubes))(*[int(s) for s in steps])
+        check(lib().rlb_batch_step(self._h, arr))
+
+    def read_tube(self, j):
+        C = self.tubes[j]["n"]
+        out = dict(n=np.empty(C), eps=np.empty(C), U=np.empty((4, C)), P=np.empty(C))
+        check(lib().rlb_batch_read(self._h, int(j), *[ctypes.c_void_p(out[k].ctypes.data)
+                                                      for k in ("n", "eps", "U", "P")], 0))
+        return out
+
+    def status(self, j):
+        fl = ctypes.c_uint32()
+        t = ctypes.c_int64()
+        check(lib().rlb_batch_status(self._h, int(j), ctypes.byref(fl), ctypes.byref(t)))
+        return fl.value, t.value

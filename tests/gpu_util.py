@@ -27,9 +27,12 @@ def field_errors(gpu, ref):
     eps, P and U^0 is max_x |F_ref|; the spatial components U^1..U^3 share
     one scale, the largest |U^j_ref| over x and j, because a component that
     vanishes in the continuum (the transverse flow of a shock tube, a pure
-    lattice artefact here) would otherwise turn rounding into a large ratio."""
+    lattice artefact here) would otherwise turn rounding into a large ratio;
+    that scale is at least 1e-3 max|U^0_ref|, so a state at rest (spatial
+    components pure rounding on both sides) is measured against the
+    4-velocity's size."""
     g, r = split(gpu), split(ref)
-    vscale = max(np.max(np.abs(r["U%d" % j])) for j in (1, 2, 3))
+    vscale = max(max(np.max(np.abs(r["U%d" % j])) for j in (1, 2, 3)), 1e-3 * np.max(np.abs(r["U0"])))
     out = {}
     for k in FIELDS:
         scale = vscale if k in ("U1", "U2", "U3") else np.max(np.abs(r[k]))
