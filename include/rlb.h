@@ -212,6 +212,68 @@ int rlb_batch_status(rlb_batch *b, int32_t tube, uint32_t *flags, int64_t *t);
 /* Releases the batch's host allocations. */
 void rlb_batch_destroy(rlb_batch *b);
 
+/* ---- serving: continuous batching of tube and box solves -------------------
+ * A server owns a worker thread and a caller-owned device pool.  Requests
+ * (a shock tube or a periodic box, each with its own precision, relaxation,
+ * step count and initial fields) are submitted at any time; the worker
+ * admits them first-come-first-served as soon as their footprint fits in
+ * the pool, and advances everything resident in rounds of at most
+ * `chunk_steps` steps: all resident tubes of one precision in one persistent
+ * launch, each box by a replayed hipGraph of chunk_steps launches.  Finished
+ * requests are read back, their memory is freed and they are reported by
+ * rlb_server_poll.  A request's result does not depend on what else is
+ * resident (the kernels never mix requests).  Times are seconds since the
+ * server was created. */
+#define RLB_REQ_TUBE 0 /* 1 x 1 x nz lattice (nx = ny = 1)                */
+#define RLB_REQ_BOX 1  /* nx x ny x nz periodic box                        */
+
+typedef struct rlb_request {
+  int32_t kind;       /* RLB_REQ_TUBE or RLB_REQ_BOX                          */
+  int32_t nx, ny, nz; /* lattice size (a tube has nx = ny = 1)                */
+  int32_t precision;  /* RLB_FP64 or RLB_MIXED                                */
+  int32_t tau_mode;   /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */
+  double tau, eta_s;
+  int64_t steps;      /* >= 0                                                  */
+  /* initial fields, nx*ny*nz host values each; copied by rlb_server_submit  */
+  const double *n, *eps, *vx, *vy, *vz;
+  /* host outputs written before the completion is reported (may be NULL);
+   * they must stay valid until then                                        */
+  double *out_n, *out_eps, *out_U4, *out_P;
+} rlb_request;
+
+typedef struct rlb_completion {
+  int64_t id;
+  int32_t rc;         /* RLB_OK, or the error that ended the request          */
+  uint32_t flags;     /* RLB_FLAG_* of this request                           */
+  double t_submit, t_admit, t_done;
+} rlb_completion;
+
+typedef struct rlb_server rlb_server;
+
+/* Device bytes one request occupies while resident (0 if invalid). */
+size_t rlb_request_bytes(const rlb_request *req);
+
+/* Starts a server on the current device over a caller-owned pool (256-byte
+ * aligned).  chunk_steps: even, >= 2.  max_tubes: how many tubes may be
+ * resident at once.  The pool must stay valid until rlb_server_destroy. */
+int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t chunk_steps, int32_t max_tubes);
+
+/* Queues a request (thread-safe).  Validates it (RLB_EINVAL, RLB_ENONPHYS
+ * for bad fields, RLB_ENOMEM if it can never fit in the pool) and copies the
+ * initial fields; *id identifies it in completions. */
+int rlb_server_submit(rlb_server *s, const rlb_request *req, int64_t *id);
+
+/* Up to `max` completions into out (thread-safe); waits up to wait_ms for
+ * the first one.  *count is the number returned. */
+int rlb_server_poll(rlb_server *s, rlb_completion *out, int32_t max, int32_t *count, int32_t wait_ms);
+
+/* Requests submitted and not yet reported, and rounds run so far. */
+int rlb_server_pending(rlb_server *s, int64_t *pending, int64_t *rounds);
+
+/* Stops the worker (pending requests are dropped) and releases the
+ * server's host resources and streams. */
+void rlb_server_destroy(rlb_server *s);
+
 /* ---- diagnostics --------------------------------------------------------- */
 const char *rlb_strerror(int code);
 const char *rlb_last_error(void);

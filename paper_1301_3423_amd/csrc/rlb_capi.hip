@@ -716,3 +716,528 @@ void rlb_batch_destroy(rlb_batch *b) {
 void rlb_destroy(rlb_solver *s) { delete s; }
 
 } // extern "C"
+
+// ---- serving -------------------------------------------------------------------
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+namespace {
+
+// First-fit allocator over the caller's pool (offsets, 256-byte granules),
+// coalescing neighbours on release.
+class PoolAlloc {
+public:
+  PoolAlloc(size_t base, size_t size) { free_[base] = size; }
+  bool alloc(size_t bytes, size_t &off) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        const size_t rem = it->second - bytes;
+        free_.erase(it);
+        if (rem) free_[off + bytes] = rem;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto &kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+private:
+  std::map<size_t, size_t> free_;
+};
+
+struct ServeReq {
+  int64_t id;
+  rlb_request r;
+  std::vector<double> fields; // n, eps, vx, vy, vz
+  double t_submit = 0, t_admit = 0;
+  size_t off = 0, bytes = 0;
+  int64_t remaining = 0;
+  // box
+  rlb_solver *box = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int stream_idx = 0;
+  // tube
+  int slot = -1;
+  int cur = 0;
+  int64_t tube_off[2] = {0, 0};
+  int32_t stride = 0;
+};
+
+constexpr int SERVE_TUBE_STREAMS = 2; // one per precision
+constexpr int SERVE_BOX_STREAMS = 4;
+constexpr int SERVE_STREAMS = SERVE_TUBE_STREAMS + SERVE_BOX_STREAMS;
+
+int64_t request_cells(const rlb_request &r) {
+  return static_cast<int64_t>(r.nx) * r.ny * r.nz;
+}
+
+bool request_valid(const rlb_request &r, std::string &why) {
+  if (r.kind != RLB_REQ_TUBE && r.kind != RLB_REQ_BOX) return why = "bad kind", false;
+  if (r.kind == RLB_REQ_TUBE && (r.nx != 1 || r.ny != 1)) return why = "a tube needs nx = ny = 1", false;
+  if (!valid_dims(r.nx, r.ny, r.nz)) return why = "bad lattice size", false;
+  if (r.precision != RLB_FP64 && r.precision != RLB_MIXED) return why = "bad precision", false;
+  rlb_tube tb{r.nz, r.tau_mode, r.tau, r.eta_s};
+  if (!valid_tube(tb)) return why = "bad relaxation", false;
+  if (r.steps < 0) return why = "negative steps", false;
+  if (!r.n || !r.eps || !r.vx || !r.vy || !r.vz) return why = "NULL field", false;
+  return true;
+}
+
+} // namespace
+
+struct rlb_server {
+  int device = 0;
+  char *pool = nullptr;
+  size_t pool_bytes = 0;
+  int chunk = 0;
+  int max_tubes = 0;
+  size_t table_bytes = 0; // front of the pool: tube descriptors, orders, status
+  PoolAlloc *alloc = nullptr;
+  rlb::TubeDesc *d_desc[2] = {nullptr, nullptr};
+  int *d_order[2] = {nullptr, nullptr};
+  unsigned *d_status = nullptr;
+  rlb::TubeDesc *h_desc[2] = {nullptr, nullptr};
+  int *h_order[2] = {nullptr, nullptr};
+  std::vector<int> free_slots;
+  hipStream_t streams[SERVE_STREAMS] = {};
+  int next_box_stream = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<ServeReq *> queue;
+  std::vector<ServeReq *> resident;
+  std::deque<rlb_completion> done;
+  bool stop = false;
+  int64_t next_id = 0;
+  int64_t pending = 0;
+  std::atomic<int64_t> rounds{0};
+  std::chrono::steady_clock::time_point t0;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+size_t tube_pair_bytes(const rlb_request &r) { return 2 * tube_buffer_bytes(r.nz, r.precision); }
+
+size_t request_bytes_of(const rlb_request &r) {
+  if (r.kind == RLB_REQ_TUBE) return tube_pair_bytes(r);
+  return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision));
+}
+
+void finish(rlb_server *sv, ServeReq *q, int rc, unsigned flags) {
+  rlb_completion c;
+  c.id = q->id;
+  c.rc = rc;
+  c.flags = flags;
+  c.t_submit = q->t_submit;
+  c.t_admit = q->t_admit;
+  c.t_done = sv->now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->done.push_back(c);
+    sv->pending -= 1;
+  }
+  sv->cv_done.notify_all();
+}
+
+void release(rlb_server *sv, ServeReq *q) {
+  if (q->graph_exec) (void)hipGraphExecDestroy(q->graph_exec);
+  if (q->graph) (void)hipGraphDestroy(q->graph);
+  if (q->box) rlb_destroy(q->box);
+  if (q->slot >= 0) sv->free_slots.push_back(q->slot);
+  if (q->bytes) sv->alloc->release(q->off, q->bytes);
+  delete q;
+}
+
+// Moves a queued request onto the device: allocate, initialise.
+int admit(rlb_server *sv, ServeReq *q) {
+  const rlb_request &r = q->r;
+  const int64_t C = request_cells(r);
+  const double *f = q->fields.data();
+  q->t_admit = sv->now();
+  q->remaining = r.steps;
+  if (r.kind == RLB_REQ_BOX) {
+    q->stream_idx = SERVE_TUBE_STREAMS + (sv->next_box_stream++ % SERVE_BOX_STREAMS);
+    rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s};
+    int rc = rlb_create(&q->box, &cfg, sv->pool + q->off, q->bytes, sv->streams[q->stream_idx]);
+    if (rc != RLB_OK) return rc;
+    return rlb_init_fields(q->box, f, f + C, f + 2 * C, f + 3 * C, f + 4 * C, 0);
+  }
+  // tube: two buffers at q->off, staging through the second one
+  const size_t eb = elem_bytes(r.precision);
+  const size_t tb = tube_buffer_bytes(r.nz, r.precision);
+  q->stride = static_cast<int32_t>(pop_stride(r.nz, r.precision));
+  q->tube_off[0] = static_cast<int64_t>(q->off / eb);
+  q->tube_off[1] = static_cast<int64_t>((q->off + tb) / eb);
+  q->cur = 0;
+  hipStream_t st = sv->streams[r.precision == RLB_FP64 ? 0 : 1];
+  double *stage = reinterpret_cast<double *>(sv->pool + q->off + tb);
+  RLB_HIP(hipMemcpyAsync(stage, f, 5 * C * sizeof(double), hipMemcpyHostToDevice, st));
+  RLB_HIP(hipMemsetAsync(sv->d_status + q->slot, 0, sizeof(unsigned), st));
+  rlb::Geom g;
+  g.nx = 1;
+  g.ny = 1;
+  g.nz = r.nz;
+  g.cells = r.nz;
+  g.stride = q->stride;
+  const dim3 grid(grid_of(C)), block(rlb::BLOCK);
+  if (r.precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_init<double>, grid, block, 0, st, stage, stage + C, stage + 2 * C, stage + 3 * C,
+                       stage + 4 * C, reinterpret_cast<double *>(sv->pool + q->off), g, sv->d_status + q->slot);
+  else
+    hipLaunchKernelGGL(rlb::k_init<float>, grid, block, 0, st, stage, stage + C, stage + 2 * C, stage + 3 * C,
+                       stage + 4 * C, reinterpret_cast<float *>(sv->pool + q->off), g, sv->d_status + q->slot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "serve k_init");
+  RLB_HIP(hipStreamSynchronize(st)); // the staged fields are consumed before the next round reuses the buffer
+  return RLB_OK;
+}
+
+// Reads a finished request's fields into its host outputs; returns rc.
+int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
+  const rlb_request &r = q->r;
+  if (r.kind == RLB_REQ_BOX) {
+    int rc = rlb_read_fields(q->box, r.out_n, r.out_eps, r.out_U4, r.out_P, 0);
+    if (rc != RLB_OK) return rc;
+    return rlb_status(q->box, &flags, nullptr);
+  }
+  const int64_t C = r.nz;
+  const size_t eb = elem_bytes(r.precision);
+  hipStream_t st = sv->streams[r.precision == RLB_FP64 ? 0 : 1];
+  double *stage = reinterpret_cast<double *>(sv->pool + static_cast<size_t>(q->tube_off[1 - q->cur]) * eb);
+  char *curp = sv->pool + static_cast<size_t>(q->tube_off[q->cur]) * eb;
+  rlb::Geom g;
+  g.nx = 1;
+  g.ny = 1;
+  g.nz = r.nz;
+  g.cells = r.nz;
+  g.stride = q->stride;
+  const dim3 grid(grid_of(C)), block(rlb::BLOCK);
+  double *dn = stage, *de = stage + C, *dU = stage + 2 * C, *dP = stage + 6 * C;
+  if (r.precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_read<double>, grid, block, 0, st, reinterpret_cast<const double *>(curp), g, dn, de, dU,
+                       dP, sv->d_status + q->slot);
+  else
+    hipLaunchKernelGGL(rlb::k_read<float>, grid, block, 0, st, reinterpret_cast<const float *>(curp), g, dn, de, dU,
+                       dP, sv->d_status + q->slot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "serve k_read");
+  if (r.out_n) RLB_HIP(hipMemcpyAsync(r.out_n, dn, C * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (r.out_eps) RLB_HIP(hipMemcpyAsync(r.out_eps, de, C * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (r.out_U4) RLB_HIP(hipMemcpyAsync(r.out_U4, dU, 4 * C * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (r.out_P) RLB_HIP(hipMemcpyAsync(r.out_P, dP, C * sizeof(double), hipMemcpyDeviceToHost, st));
+  unsigned h = 0;
+  RLB_HIP(hipMemcpyAsync(&h, sv->d_status + q->slot, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  RLB_HIP(hipStreamSynchronize(st));
+  flags = h;
+  return RLB_OK;
+}
+
+// Advances one box by `steps`: full chunks replay a captured graph.
+int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
+  if (steps == sv->chunk) {
+    if (!q->graph_exec) {
+      hipStream_t st = sv->streams[q->stream_idx];
+      RLB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int64_t t_before = q->box->t;
+      const int cur_before = q->box->cur;
+      int rc = rlb_step(q->box, steps);
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(st, &gr);
+      q->box->t = t_before; // capture issued nothing: undo the host bookkeeping
+      q->box->cur = cur_before;
+      if (rc != RLB_OK) return rc;
+      if (e != hipSuccess) return hip_fail(e, "serve graph capture");
+      q->graph = gr;
+      RLB_HIP(hipGraphInstantiate(&q->graph_exec, gr, nullptr, nullptr, 0));
+    }
+    RLB_HIP(hipGraphLaunch(q->graph_exec, sv->streams[q->stream_idx]));
+    q->box->t += steps; // chunk is even: the current buffer is unchanged
+    return RLB_OK;
+  }
+  return rlb_step(q->box, steps);
+}
+
+int tubes_advance(rlb_server *sv, int prec) {
+  // all resident tubes of this precision, one persistent launch
+  std::vector<ServeReq *> tubes;
+  for (ServeReq *q : sv->resident)
+    if (q->r.kind == RLB_REQ_TUBE && q->r.precision == prec && q->remaining > 0) tubes.push_back(q);
+  if (tubes.empty()) return RLB_OK;
+  const int p = prec == RLB_FP64 ? 0 : 1;
+  std::stable_sort(tubes.begin(), tubes.end(), [&](ServeReq *a, ServeReq *b) {
+    return static_cast<double>(a->r.nz) * std::min<int64_t>(a->remaining, sv->chunk) >
+           static_cast<double>(b->r.nz) * std::min<int64_t>(b->remaining, sv->chunk);
+  });
+  int k = 0;
+  for (ServeReq *q : tubes) {
+    rlb::TubeDesc &d = sv->h_desc[p][q->slot];
+    d.off[0] = q->tube_off[0];
+    d.off[1] = q->tube_off[1];
+    d.steps = std::min<int64_t>(q->remaining, sv->chunk);
+    d.n = q->r.nz;
+    d.stride = q->stride;
+    d.cur = q->cur;
+    d.mode = q->r.tau_mode == RLB_TAU_ETA_S ? 1 : 0;
+    d.tau = q->r.tau;
+    d.eta_s = q->r.eta_s;
+    sv->h_order[p][k++] = q->slot;
+  }
+  hipStream_t st = sv->streams[p];
+  RLB_HIP(hipMemcpyAsync(sv->d_desc[p], sv->h_desc[p], sv->max_tubes * sizeof(rlb::TubeDesc), hipMemcpyHostToDevice, st));
+  RLB_HIP(hipMemcpyAsync(sv->d_order[p], sv->h_order[p], k * sizeof(int), hipMemcpyHostToDevice, st));
+  if (prec == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_tubes<double>, dim3(k), dim3(rlb::TUBE_BLOCK), 0, st, reinterpret_cast<double *>(sv->pool),
+                       sv->d_desc[p], sv->d_order[p], sv->d_status);
+  else
+    hipLaunchKernelGGL(rlb::k_tubes<float>, dim3(k), dim3(rlb::TUBE_BLOCK), 0, st, reinterpret_cast<float *>(sv->pool),
+                       sv->d_desc[p], sv->d_order[p], sv->d_status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "serve k_tubes");
+  for (ServeReq *q : tubes) {
+    const int64_t s = std::min<int64_t>(q->remaining, sv->chunk);
+    q->cur ^= static_cast<int>(s & 1);
+    q->remaining -= s;
+  }
+  return RLB_OK;
+}
+
+void serve_loop(rlb_server *sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    // admission: first come, first served, as long as memory and slots allow
+    std::vector<ServeReq *> admitted;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->resident.empty(); });
+      if (sv->stop) return;
+      while (!sv->queue.empty()) {
+        ServeReq *q = sv->queue.front();
+        if (q->r.kind == RLB_REQ_TUBE && sv->free_slots.empty()) break;
+        size_t off = 0;
+        if (!sv->alloc->alloc(q->bytes, off)) break;
+        q->off = off;
+        if (q->r.kind == RLB_REQ_TUBE) {
+          q->slot = sv->free_slots.back();
+          sv->free_slots.pop_back();
+        }
+        sv->queue.pop_front();
+        admitted.push_back(q);
+      }
+    }
+    for (ServeReq *q : admitted) {
+      const int rc = admit(sv, q);
+      if (rc != RLB_OK) {
+        finish(sv, q, rc, 0);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        release(sv, q);
+        continue;
+      }
+      sv->resident.push_back(q);
+    }
+    if (sv->resident.empty()) continue;
+    // one round
+    int rc = tubes_advance(sv, RLB_FP64);
+    if (rc == RLB_OK) rc = tubes_advance(sv, RLB_MIXED);
+    for (ServeReq *q : sv->resident) {
+      if (rc != RLB_OK) break;
+      if (q->r.kind != RLB_REQ_BOX || q->remaining == 0) continue;
+      const int64_t s = std::min<int64_t>(q->remaining, sv->chunk);
+      rc = box_advance(sv, q, s);
+      q->remaining -= s;
+    }
+    for (int i = 0; i < SERVE_STREAMS; ++i) (void)hipStreamSynchronize(sv->streams[i]);
+    sv->rounds += 1;
+    // completions
+    std::vector<ServeReq *> keep;
+    for (ServeReq *q : sv->resident) {
+      if (rc == RLB_OK && q->remaining > 0) {
+        keep.push_back(q);
+        continue;
+      }
+      unsigned flags = 0;
+      const int crc = rc != RLB_OK ? rc : complete(sv, q, flags);
+      finish(sv, q, crc, flags);
+      std::lock_guard<std::mutex> lk(sv->mu);
+      release(sv, q);
+    }
+    sv->resident.swap(keep);
+  }
+}
+
+} // namespace
+
+extern "C" {
+
+size_t rlb_request_bytes(const rlb_request *req) {
+  if (!req) return 0;
+  std::string why;
+  if (!request_valid(*req, why)) return 0;
+  return request_bytes_of(*req);
+}
+
+int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t chunk_steps, int32_t max_tubes) {
+  if (!out || !d_pool) return fail(RLB_EINVAL, "rlb_server_create: NULL argument");
+  *out = nullptr;
+  if (chunk_steps < 2 || chunk_steps % 2) return fail(RLB_EINVAL, "rlb_server_create: chunk_steps must be even and >= 2");
+  if (max_tubes < 1) return fail(RLB_EINVAL, "rlb_server_create: max_tubes must be >= 1");
+  if (reinterpret_cast<uintptr_t>(d_pool) % 256 != 0) return fail(RLB_EINVAL, "rlb_server_create: pool not 256-byte aligned");
+  const size_t table = 2 * align256(max_tubes * sizeof(rlb::TubeDesc)) + 2 * align256(max_tubes * sizeof(int)) +
+                       align256(max_tubes * sizeof(unsigned));
+  if (pool_bytes <= table) return fail(RLB_ENOMEM, "rlb_server_create: pool too small");
+  rlb_server *sv = new (std::nothrow) rlb_server();
+  if (!sv) return fail(RLB_EINVAL, "rlb_server_create: out of host memory");
+  RLB_HIP(hipGetDevice(&sv->device));
+  sv->pool = static_cast<char *>(d_pool);
+  sv->pool_bytes = pool_bytes;
+  sv->chunk = chunk_steps;
+  sv->max_tubes = max_tubes;
+  sv->table_bytes = table;
+  char *p = sv->pool;
+  for (int k = 0; k < 2; ++k) {
+    sv->d_desc[k] = reinterpret_cast<rlb::TubeDesc *>(p);
+    p += align256(max_tubes * sizeof(rlb::TubeDesc));
+    sv->d_order[k] = reinterpret_cast<int *>(p);
+    p += align256(max_tubes * sizeof(int));
+  }
+  sv->d_status = reinterpret_cast<unsigned *>(p);
+  // requests are placed after the tables; allocator offsets are from the pool start
+  sv->alloc = new PoolAlloc(table, pool_bytes - table);
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_desc[k]), max_tubes * sizeof(rlb::TubeDesc), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_order[k]), max_tubes * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      rlb_server_destroy(sv);
+      return hip_fail(e, "rlb_server_create: pinned tables");
+    }
+    std::memset(sv->h_desc[k], 0, max_tubes * sizeof(rlb::TubeDesc));
+  }
+  for (int i = 0; i < SERVE_STREAMS; ++i) {
+    hipError_t e = hipStreamCreateWithFlags(&sv->streams[i], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      rlb_server_destroy(sv);
+      return hip_fail(e, "rlb_server_create: streams");
+    }
+  }
+  for (int j = max_tubes - 1; j >= 0; --j) sv->free_slots.push_back(j);
+  sv->t0 = std::chrono::steady_clock::now();
+  sv->worker = std::thread(serve_loop, sv);
+  *out = sv;
+  return RLB_OK;
+}
+
+int rlb_server_submit(rlb_server *sv, const rlb_request *req, int64_t *id) {
+  if (!sv || !req) return fail(RLB_EINVAL, "rlb_server_submit: NULL argument");
+  std::string why;
+  if (!request_valid(*req, why)) return fail(RLB_EINVAL, "rlb_server_submit: " + why);
+  const int64_t C = request_cells(*req);
+  const double *arrs[5] = {req->n, req->eps, req->vx, req->vy, req->vz};
+  for (auto a : arrs)
+    if (!finite_all(a, C)) return fail(RLB_ENONPHYS, "rlb_server_submit: non-finite value");
+  for (int64_t c = 0; c < C; ++c) {
+    const double v2 = req->vx[c] * req->vx[c] + req->vy[c] * req->vy[c] + req->vz[c] * req->vz[c];
+    if (!(req->n[c] > 0.0) || !(req->eps[c] > 0.0) || !(v2 < 1.0))
+      return fail(RLB_ENONPHYS, "rlb_server_submit: cell " + std::to_string(c) + " has n<=0, eps<=0 or |v|>=1");
+  }
+  const size_t bytes = request_bytes_of(*req);
+  if (bytes > sv->pool_bytes - sv->table_bytes) return fail(RLB_ENOMEM, "rlb_server_submit: request can never fit in the pool");
+  ServeReq *q = new (std::nothrow) ServeReq();
+  if (!q) return fail(RLB_EINVAL, "rlb_server_submit: out of host memory");
+  q->r = *req;
+  q->fields.resize(5 * C);
+  for (int k = 0; k < 5; ++k) std::memcpy(q->fields.data() + k * C, arrs[k], C * sizeof(double));
+  q->r.n = q->r.eps = q->r.vx = q->r.vy = q->r.vz = nullptr;
+  q->bytes = bytes;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    q->id = sv->next_id++;
+    q->t_submit = sv->now();
+    sv->queue.push_back(q);
+    sv->pending += 1;
+  }
+  sv->cv_work.notify_all();
+  if (id) *id = q->id;
+  return RLB_OK;
+}
+
+int rlb_server_poll(rlb_server *sv, rlb_completion *out, int32_t max, int32_t *count, int32_t wait_ms) {
+  if (!sv || !out || !count || max < 1) return fail(RLB_EINVAL, "rlb_server_poll: bad argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (sv->done.empty() && wait_ms > 0)
+    sv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !sv->done.empty(); });
+  int n = 0;
+  while (n < max && !sv->done.empty()) {
+    out[n++] = sv->done.front();
+    sv->done.pop_front();
+  }
+  *count = n;
+  return RLB_OK;
+}
+
+int rlb_server_pending(rlb_server *sv, int64_t *pending, int64_t *rounds) {
+  if (!sv) return fail(RLB_EINVAL, "rlb_server_pending: NULL server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (pending) *pending = sv->pending;
+  if (rounds) *rounds = sv->rounds.load();
+  return RLB_OK;
+}
+
+void rlb_server_destroy(rlb_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (int i = 0; i < SERVE_STREAMS; ++i)
+    if (sv->streams[i]) (void)hipStreamSynchronize(sv->streams[i]);
+  for (ServeReq *q : sv->resident) release(sv, q);
+  for (ServeReq *q : sv->queue) {
+    q->bytes = 0;
+    q->slot = -1;
+    release(sv, q);
+  }
+  for (int i = 0; i < SERVE_STREAMS; ++i)
+    if (sv->streams[i]) (void)hipStreamDestroy(sv->streams[i]);
+  for (int k = 0; k < 2; ++k) {
+    if (sv->h_desc[k]) (void)hipHostFree(sv->h_desc[k]);
+    if (sv->h_order[k]) (void)hipHostFree(sv->h_order[k]);
+  }
+  delete sv->alloc;
+  delete sv;
+}
+
+} // extern "C"

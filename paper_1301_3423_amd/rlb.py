@@ -29,7 +29,10 @@ MAX_Q = 128
 EXPORTS = ("rlb_lattice_info", "rlb_state_bytes", "rlb_create", "rlb_init_fields", "rlb_step",
            "rlb_read_fields", "rlb_conserved", "rlb_status", "rlb_save", "rlb_load", "rlb_destroy",
            "rlb_batch_bytes", "rlb_batch_create", "rlb_batch_init", "rlb_batch_step", "rlb_batch_read",
-           "rlb_batch_status", "rlb_batch_destroy", "rlb_strerror", "rlb_last_error")
+           "rlb_batch_status", "rlb_batch_destroy", "rlb_request_bytes", "rlb_server_create",
+           "rlb_server_submit", "rlb_server_poll", "rlb_server_pending", "rlb_server_destroy",
+           "rlb_strerror", "rlb_last_error")
+REQ_TUBE, REQ_BOX = 0, 1
 
 
 class RLBError(RuntimeError):
@@ -59,6 +62,22 @@ class Config(ctypes.Structure):
 class Tube(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("eta_s", ctypes.c_double)]
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("eta_s", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("n", _DP), ("eps", _DP), ("vx", _DP), ("vy", _DP), ("vz", _DP),
+                ("out_n", _DP), ("out_eps", _DP), ("out_U4", _DP), ("out_P", _DP)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("rc", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +113,14 @@ def lib():
         L.rlb_batch_status.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64)]
         L.rlb_batch_destroy.argtypes = [vp]
         L.rlb_batch_destroy.restype = None
+        L.rlb_request_bytes.argtypes = [ctypes.POINTER(Request)]
+        L.rlb_request_bytes.restype = ctypes.c_size_t
+        L.rlb_server_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t, i32, i32]
+        L.rlb_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]
+        L.rlb_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32), i32]
+        L.rlb_server_pending.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.rlb_server_destroy.argtypes = [vp]
+        L.rlb_server_destroy.restype = None
         L.rlb_strerror.argtypes = [ctypes.c_int]
         L.rlb_strerror.restype = ctypes.c_char_p
         L.rlb_last_error.restype = ctypes.c_char_p
@@ -291,3 +318,89 @@ class Batch:
         t = ctypes.c_int64()
         check(lib().rlb_batch_status(self._h, int(j), ctypes.byref(fl), ctypes.byref(t)))
         return fl.value, t.value
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def make_request(kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True):
+    """A Request plus the numpy arrays it points to (keep them alive)."""
+    nx, ny, nz = shape
+    if (tau is None) == (eta_s is None):
+        raise ValueError("give exactly one of tau, eta_s")
+    ins = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)).ravel() for a in fields]
+    C = nx * ny * nz
+    outs = dict(n=np.empty(C), eps=np.empty(C), U=np.empty((4, C)), P=np.empty(C)) if outputs else None
+    r = Request(REQ_TUBE if kind == "tube" else REQ_BOX, nx, ny, nz, _prec(precision),
+                TAU_FIXED if tau is not None else TAU_ETA_S, float(tau or 0.0), float(eta_s or 0.0), int(steps),
+                *[_dp(a) for a in ins],
+                *([_dp(outs[k]) for k in ("n", "eps", "U", "P")] if outs else [None] * 4))
+    return r, ins, outs
+
+
+def request_bytes(kind, shape, precision):
+    nx, ny, nz = shape
+    r = Request(REQ_TUBE if kind == "tube" else REQ_BOX, nx, ny, nz, _prec(precision), TAU_FIXED, 1.0, 0.0, 0)
+    one = np.ones(1)
+    r.n = r.eps = r.vx = r.vy = r.vz = _dp(one)
+    return lib().rlb_request_bytes(ctypes.byref(r))
+
+
+class Server:
+    """Continuous-batching server over a torch-owned device pool."""
+
+    def __init__(self, pool_bytes, chunk_steps=50, max_tubes=1024, device=None):
+        import torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(lib().rlb_server_create(ctypes.byref(h), ctypes.c_void_p(self.pool.data_ptr()), int(pool_bytes),
+                                      int(chunk_steps), int(max_tubes)))
+        self._h = h
+        self._live = {}      # id -> (request, inputs, outputs)
+
+    def submit(self, kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True):
+        r, ins, outs = make_request(kind, shape, precision, steps, fields, tau, eta_s, outputs)
+        rid = ctypes.c_int64()
+        check(lib().rlb_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._live[rid.value] = (r, outs)    # outputs stay alive until reported
+        return rid.value
+
+    def poll(self, max_n=256, wait_ms=0):
+        buf = (Completion * max_n)()
+        cnt = ctypes.c_int32()
+        check(lib().rlb_server_poll(self._h, buf, max_n, ctypes.byref(cnt), int(wait_ms)))
+        out = []
+        for c in buf[:cnt.value]:
+            _, outs = self._live.pop(c.id, (None, None))
+            out.append(dict(id=c.id, rc=c.rc, flags=c.flags, t_submit=c.t_submit, t_admit=c.t_admit,
+                            t_done=c.t_done, fields=outs))
+        return out
+
+    def pending(self):
+        p = ctypes.c_int64()
+        r = ctypes.c_int64()
+        check(lib().rlb_server_pending(self._h, ctypes.byref(p), ctypes.byref(r)))
+        return p.value, r.value
+
+    def drain(self, timeout_s=600.0):
+        """Poll until every submitted request has been reported."""
+        import time
+        done = []
+        t_end = time.time() + timeout_s
+        while self.pending()[0] > 0:
+            if time.time() > t_end:
+                raise TimeoutError("server did not finish in %.0f s" % timeout_s)
+            done.extend(self.poll(wait_ms=100))
+        done.extend(self.poll())
+        return done
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rlb_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

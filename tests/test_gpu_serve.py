@@ -1,0 +1,89 @@
+"""The continuous-batching server: results are the same alone and in a mix
+(bitwise, both precisions), match the oracle, admission respects the pool,
+and a failing request fails alone."""
+import numpy as np
+import pytest
+
+from gpu_util import field_errors, note
+from oracle import rlb as orlb
+from paper_1301_3423_amd import inputs, rlb
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    # kind, shape, precision, steps, relaxation, field recipe
+    ("tube", (1, 1, 300), "fp64", 60, dict(eta_s=0.1), ("tube", 0.6)),
+    ("tube", (1, 1, 129), "mixed", 35, dict(tau=0.9), ("tube", 0.8)),
+    ("box", (12, 10, 9), "fp64", 14, dict(eta_s=0.2), ("box", 0.5, 5)),
+    ("box", (64, 4, 3), "mixed", 9, dict(tau=1.0), ("box", 0.4, 6)),
+    ("tube", (1, 1, 77), "mixed", 0, dict(eta_s=0.5), ("tube", 0.7)),
+    ("box", (9, 8, 7), "mixed", 23, dict(eta_s=0.3), ("box", 0.5, 7)),
+    ("tube", (1, 1, 1000), "fp64", 41, dict(eta_s=0.2), ("tube", 0.5)),
+]
+
+
+def _fields(recipe, shape):
+    if recipe[0] == "tube":
+        return inputs.shock_tube(shape[2], 1.0, recipe[1])
+    return inputs.random_box(*shape, recipe[1], seed=recipe[2])
+
+
+def _run(server, items):
+    ids = [server.submit(k, sh, pr, st, _fields(fr, sh), **rx) for (k, sh, pr, st, rx, fr) in items]
+    done = {c["id"]: c for c in server.drain(timeout_s=300)}
+    return [done[i] for i in ids]
+
+
+def test_mix_equals_alone_and_matches_oracle(lat):
+    sv = rlb.Server(2 << 30, chunk_steps=8, max_tubes=64)
+    mixed = _run(sv, MIX)
+    _, rounds = sv.pending()
+    note("mix: %d requests in %d rounds" % (len(MIX), rounds))
+    for item, got in zip(MIX, mixed):
+        kind, shape, prec, steps, rx, fr = item
+        alone_sv = rlb.Server(1 << 30, chunk_steps=8, max_tubes=4)
+        alone = _run(alone_sv, [item])[0]
+        alone_sv.close()
+        assert got["rc"] == 0 and alone["rc"] == 0
+        for k in ("n", "eps", "U", "P"):
+            assert np.array_equal(got["fields"][k], alone["fields"][k]), (item, k)
+        o = orlb.Solver(*shape, lat=lat, **rx)
+        o.init_fields(*_fields(fr, shape))
+        o.step(steps)
+        err = field_errors(got["fields"], o.read_fields())
+        tol = 1e-12 if prec == "fp64" else 1e-5
+        note("%s %s %s steps %d: max err %.2e flags %d" % (kind, shape, prec, steps, max(err.values()), got["flags"]))
+        assert got["flags"] == 0
+        assert max(err.values()) <= tol, (item, err)
+    sv.close()
+
+
+def test_admission_waits_for_memory():
+    """A pool that holds one 32^3 FP64 box at a time: the second waits."""
+    one = rlb.request_bytes("box", (32, 32, 32), "fp64")
+    sv = rlb.Server(one + one // 2, chunk_steps=4, max_tubes=4)
+    f = inputs.random_box(32, 32, 32, 0.3, seed=1)
+    a = sv.submit("box", (32, 32, 32), "fp64", 6, f, tau=1.0)
+    b = sv.submit("box", (32, 32, 32), "fp64", 6, f, tau=1.0)
+    done = {c["id"]: c for c in sv.drain(timeout_s=120)}
+    assert done[a]["rc"] == 0 and done[b]["rc"] == 0
+    assert done[b]["t_admit"] >= done[a]["t_done"] - 1e-3
+    for k in ("n", "eps", "U", "P"):
+        assert np.array_equal(done[a]["fields"][k], done[b]["fields"][k])
+    with pytest.raises(rlb.RLBError) as e:
+        sv.submit("box", (64, 64, 64), "fp64", 1, inputs.random_box(64, 64, 64, 0.3, 1), tau=1.0)
+    assert e.value.code == rlb.ENOMEM
+    sv.close()
+
+
+def test_failing_request_fails_alone():
+    """A strong shock at eta/s = 0.01 goes non-physical (a property of the
+    scheme at this viscosity); the tube and box served with it do not."""
+    sv = rlb.Server(1 << 30, chunk_steps=10, max_tubes=8)
+    bad = sv.submit("tube", (1, 1, 400), "mixed", 60, inputs.shock_tube(400, 1.0, 0.5), eta_s=0.01)
+    good = sv.submit("tube", (1, 1, 400), "mixed", 60, inputs.shock_tube(400, 1.0, 0.8), eta_s=0.1)
+    box = sv.submit("box", (16, 16, 16), "mixed", 20, inputs.random_box(16, 16, 16, 0.3, 2), eta_s=0.2)
+    done = {c["id"]: c for c in sv.drain(timeout_s=120)}
+    assert done[bad]["flags"] != 0
+    assert done[good]["flags"] == 0 and done[box]["flags"] == 0
+    sv.close()
