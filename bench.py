@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tubes", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
     return ap.parse_args()
@@ -156,13 +157,80 @@ def run_tubes(precision, ntubes=512, steps=500, seed=4):
                 achieved_gbs=lu * bpl / (ms * 1e-3) / 1e9, tubes_flagged=sum(1 for f in flags if f))
 
 
+def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
+    """Continuous batching under Poisson arrivals: capacity from a saturated
+    burst, then nreq requests at rate load * capacity."""
+    import torch
+    from paper_1301_3423_amd import inputs, rlb
+    torch.cuda.empty_cache()
+    reqs = inputs.serve_requests(nreq, seed)
+    cache = {}
+    t0 = time.perf_counter()
+    fields = [inputs.request_fields(r, cache) for r in reqs]
+    print("bench: serving: %d requests generated in %.1f s" % (nreq, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+
+    def submit(sv, r, f):
+        return sv.submit(r["kind"], r["shape"], r["precision"], r["steps"], f, eta_s=r["eta_s"], outputs=True)
+
+    # capacity: a burst of the first requests, all submitted at once
+    nburst = min(120, nreq)
+    sv = rlb.Server(int(pool_gib) << 30, chunk_steps=chunk, max_tubes=2048)
+    tb = time.perf_counter()
+    for r, f in zip(reqs[:nburst], fields[:nburst]):
+        submit(sv, r, f)
+    done = sv.drain(timeout_s=600)
+    burst_s = time.perf_counter() - tb
+    sv.close()
+    capacity = nburst / burst_s
+    rate = load * capacity
+    print("bench: serving capacity %.1f solves/s; Poisson rate %.1f/s" % (capacity, rate),
+          file=sys.stderr, flush=True)
+    # Poisson arrivals
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    sv = rlb.Server(int(pool_gib) << 30, chunk_steps=chunk, max_tubes=2048)
+    done = []
+    start = time.perf_counter()
+    for k, (r, f) in enumerate(zip(reqs, fields)):
+        while True:
+            now = time.perf_counter() - start
+            if now >= arrivals[k]:
+                break
+            done.extend(sv.poll(wait_ms=max(1, int(1000 * min(arrivals[k] - now, 0.05)))))
+        submit(sv, r, f)
+        if (k + 1) % 200 == 0:
+            print("bench: serving: %d submitted, %d done" % (k + 1, len(done)), file=sys.stderr, flush=True)
+    done.extend(sv.drain(timeout_s=900))
+    makespan = time.perf_counter() - start
+    _, rounds = sv.pending()
+    sv.close()
+    lat = np.array([c["t_done"] - c["t_submit"] for c in done])
+    kinds = {}
+    for c, r in zip(sorted(done, key=lambda c: c["id"]), reqs):
+        kinds.setdefault(r["kind"], []).append(c["t_done"] - c["t_submit"])
+    return {
+        "workload": "%d requests, Poisson arrivals at %.2f x measured capacity; 70%% tubes (N 200-8000, "
+                    "100-2000 steps), 30%% boxes (32^3-128^3, |v|<=0.6, 200-1000 steps), eta/s U(0.01,0.5), "
+                    "FP64/mixed 50/50" % (nreq, load),
+        "capacity_solves_per_s": round(capacity, 2), "arrival_rate_per_s": round(rate, 2),
+        "solves_per_s": round(len(done) / makespan, 2),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        "p50_tube_s": round(float(np.percentile(kinds.get("tube", [0]), 50)), 4),
+        "p50_box_s": round(float(np.percentile(kinds.get("box", [0]), 50)), 4),
+        "flagged": int(sum(1 for c in done if c["flags"])), "errors": int(sum(1 for c in done if c["rc"])),
+        "rounds": int(rounds), "chunk_steps": chunk, "completed": len(done),
+    }
+
+
 def cpu_baseline(vmax, eta_s):
     """The FP64 oracle on a bounded sample of the same workload."""
     from threadpoolctl import threadpool_limits
     import oracle
     from oracle import rlb as orlb
     from paper_1301_3423_amd import inputs
-    edge, steps = 48, 3
+    edge, steps = 64, 10
     with threadpool_limits(limits=1):
         lat = oracle.load_lattice()
         o = orlb.Solver(edge, edge, edge, lat=lat, eta_s=eta_s)
@@ -207,6 +275,11 @@ def main():
             tubes[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "launch_ms": round(r["ms"], 3),
                            "achieved_GBps": round(r["achieved_gbs"], 1), "cells": r["cells"],
                            "tubes_flagged": r["tubes_flagged"]}
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args.serve_requests)
+        print("bench: serving p50 %.3f s p99 %.3f s, %.1f solves/s" % (
+            serving["p50_latency_s"], serving["p99_latency_s"], serving["solves_per_s"]), file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.vmax, args.eta_s)
     mixed_kernel = "k_step_row<float>" if edge % 64 == 0 else "k_step<float>"
     line = {
@@ -248,6 +321,8 @@ def main():
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",
                          **tubes}
+    if serving is not None:
+        line["serving"] = serving
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

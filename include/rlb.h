@@ -217,9 +217,10 @@ void rlb_batch_destroy(rlb_batch *b);
  * (a shock tube or a periodic box, each with its own precision, relaxation,
  * step count and initial fields) are submitted at any time; the worker
  * admits them first-come-first-served as soon as their footprint fits in
- * the pool, and advances everything resident in rounds of at most
- * `chunk_steps` steps: all resident tubes of one precision in one persistent
- * launch, each box by a replayed hipGraph of chunk_steps launches.  Finished
+ * the pool, and advances everything resident in rounds: each box by
+ * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), each
+ * tube by max(chunk_steps, chunk_steps * 4096 / nz) steps, all resident
+ * tubes of one precision in one persistent launch.  Finished
  * requests are read back, their memory is freed and they are reported by
  * rlb_server_poll.  A request's result does not depend on what else is
  * resident (the kernels never mix requests).  Times are seconds since the

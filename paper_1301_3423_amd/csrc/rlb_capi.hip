@@ -990,6 +990,16 @@ int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
   return rlb_step(q->box, steps);
 }
 
+// Steps a resident tube takes in one round: at least chunk, and as many as
+// fit in chunk * TUBE_ROUND_CELLS lattice updates, so short tubes finish in
+// few rounds while a round stays about as long as a box chunk.
+constexpr int64_t TUBE_ROUND_CELLS = 4096;
+
+int64_t tube_round_steps(const rlb_server *sv, const ServeReq *q) {
+  const int64_t budget = static_cast<int64_t>(sv->chunk) * TUBE_ROUND_CELLS / std::max<int64_t>(q->r.nz, 1);
+  return std::min<int64_t>(q->remaining, std::max<int64_t>(sv->chunk, budget));
+}
+
 int tubes_advance(rlb_server *sv, int prec) {
   // all resident tubes of this precision, one persistent launch
   std::vector<ServeReq *> tubes;
@@ -998,15 +1008,15 @@ int tubes_advance(rlb_server *sv, int prec) {
   if (tubes.empty()) return RLB_OK;
   const int p = prec == RLB_FP64 ? 0 : 1;
   std::stable_sort(tubes.begin(), tubes.end(), [&](ServeReq *a, ServeReq *b) {
-    return static_cast<double>(a->r.nz) * std::min<int64_t>(a->remaining, sv->chunk) >
-           static_cast<double>(b->r.nz) * std::min<int64_t>(b->remaining, sv->chunk);
+    return static_cast<double>(a->r.nz) * tube_round_steps(sv, a) >
+           static_cast<double>(b->r.nz) * tube_round_steps(sv, b);
   });
   int k = 0;
   for (ServeReq *q : tubes) {
     rlb::TubeDesc &d = sv->h_desc[p][q->slot];
     d.off[0] = q->tube_off[0];
     d.off[1] = q->tube_off[1];
-    d.steps = std::min<int64_t>(q->remaining, sv->chunk);
+    d.steps = tube_round_steps(sv, q);
     d.n = q->r.nz;
     d.stride = q->stride;
     d.cur = q->cur;
@@ -1027,7 +1037,7 @@ int tubes_advance(rlb_server *sv, int prec) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "serve k_tubes");
   for (ServeReq *q : tubes) {
-    const int64_t s = std::min<int64_t>(q->remaining, sv->chunk);
+    const int64_t s = tube_round_steps(sv, q);
     q->cur ^= static_cast<int>(s & 1);
     q->remaining -= s;
   }

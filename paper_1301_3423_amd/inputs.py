@@ -15,6 +15,11 @@ shock_tube   the Riemann problem of Sec. III: at rest, T = T_L for
              z < nz/2 and T_R otherwise.
 tube_batch   the parameters of many shock tubes: lengths, temperature
              ratios and eta/s drawn from a seeded generator.
+serve_requests  a stream of solve requests for the serving benchmark: 70 %
+             shock tubes (N ~ U{200..8000}, 100..2000 steps, T_L/T_R ~
+             U(1.1, 2)), 30 % periodic boxes (edge ~ U{32..128}, |v| <= 0.6,
+             200..1000 steps), eta/s ~ U(0.01, 0.5), float64 or mixed
+             precision with equal odds.
 """
 import numpy as np
 
@@ -32,12 +37,14 @@ def _modes(rng, nmodes=8):
 
 
 def _field(modes, nx, ny, nz):
-    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx,
-                          indexing="ij")
-    g = np.zeros((nz, ny, nx))
-    for k, a, ph in modes:
-        g += a * np.cos(2.0 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
-    return g
+    """sum_j a_j cos(2 pi k_j . (x/nx, y/ny, z/nz) + phi_j) on the cell
+    indices: the real part of a sum of separable complex exponentials,
+    formed as one (z y) x j by j x x product."""
+    ex = lambda k, n: np.exp(2j * np.pi * k * np.arange(n) / n)
+    A = np.stack([(a * np.exp(1j * ph) * ex(k[2], nz))[:, None] * ex(k[1], ny)[None, :]
+                  for k, a, ph in modes], axis=-1).reshape(nz * ny, len(modes))
+    B = np.stack([ex(k[0], nx) for k, a, ph in modes], axis=0)
+    return (A @ B).real.reshape(nz, ny, nx)
 
 
 def random_box(nx, ny, nz, v_max, seed):
@@ -80,3 +87,39 @@ def tube_batch(ntubes, seed, n_min=200, n_max=4000):
         es = float(rng.choice(ETA_S_CHOICES))
         out.append(dict(N=N, T_left=1.0, T_right=1.0 / r, eta_s=es))
     return out
+
+
+def serve_requests(nreq, seed=5):
+    """Request descriptions (no fields): dicts with kind, shape, precision,
+    steps, eta_s and the field recipe."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nreq):
+        tube = rng.uniform() < 0.7
+        if tube:
+            N = int(rng.integers(200, 8001))
+            steps = int(rng.integers(100, 2001))
+            ratio = float(rng.uniform(1.1, 2.0))
+            req = dict(kind="tube", shape=(1, 1, N), steps=steps, T_right=1.0 / ratio)
+        else:
+            e = int(rng.integers(32, 129))
+            steps = int(rng.integers(200, 1001))
+            req = dict(kind="box", shape=(e, e, e), steps=steps, v_max=0.6)
+        req["eta_s"] = float(rng.uniform(0.01, 0.5))
+        req["precision"] = "fp64" if rng.uniform() < 0.5 else "mixed"
+        out.append(req)
+    return out
+
+
+def request_fields(req, cache=None):
+    """Initial fields of a request; boxes of one edge share one field (seed =
+    edge), cached in `cache` if given."""
+    if req["kind"] == "tube":
+        return shock_tube(req["shape"][2], 1.0, req["T_right"])
+    e = req["shape"][0]
+    if cache is not None and e in cache:
+        return cache[e]
+    f = random_box(e, e, e, req["v_max"], seed=e)
+    if cache is not None:
+        cache[e] = f
+    return f
