@@ -121,15 +121,31 @@ def run_box(edge, precision, fields, steps, warmup, eta_s):
     from paper_1301_3423_amd import rlb
     s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
     s.init_fields(*fields)
+    c0 = s.conserved()
     ms, wall = time_steps(s, steps, warmup)
+    c1 = s.conserved()
     flags, t = s.status()
+    read = s.read_fields()
     cells = edge ** 3
     b = 8 if precision == "fp64" else 4
     bytes_per_launch = 2 * Q * b * cells
     out = dict(ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, wall_s=wall, flags=flags,
-               achieved_gbs=bytes_per_launch / (ms * 1e-3) / 1e9, bytes_per_launch=bytes_per_launch)
+               achieved_gbs=bytes_per_launch / (ms * 1e-3) / 1e9, bytes_per_launch=bytes_per_launch,
+               fields=read, t=t, conservation_drift=float(np.max(np.abs(c1 - c0)) / abs(c0[1])))
     del s
     return out
+
+
+def field_error_summary(a, b):
+    """Max-norm relative error per field; the 4-velocity is compared as a
+    4-vector (all components against max |U^mu|), as in the parity tests."""
+    out = {}
+    for k in ("n", "eps", "P"):
+        out[k] = float(np.max(np.abs(a[k] - b[k])) / np.max(np.abs(b[k])))
+    us = float(np.max(np.abs(b["U"])))
+    for j in range(4):
+        out["U%d" % j] = float(np.max(np.abs(a["U"][j] - b["U"][j])) / us)
+    return {k: float("%.3e" % v) for k, v in out.items()}
 
 
 def run_tubes(precision, ntubes=512, steps=500, seed=4):
@@ -304,6 +320,7 @@ def main():
                      "traffic": profiled_traffic(mixed_kernel, edge),
                      "kernel": mixed_kernel, "algorithmic_bytes_per_launch": mixed["bytes_per_launch"]},
         "status_flags": mixed["flags"],
+        "conservation_drift": mixed["conservation_drift"],
         "copy_GBps": round(copy_gbs, 1),
     }
     if fp64 is not None:
@@ -316,7 +333,14 @@ def main():
                                      "kernel": "k_step<double>",
                                      "algorithmic_bytes_per_launch": fp64["bytes_per_launch"]},
                         "status_flags": fp64["flags"],
+                        "conservation_drift": fp64["conservation_drift"],
                         "mixed_over_fp64": round(mixed["mlups"] / fp64["mlups"], 3)}
+        # both runs start from the same fields and take the same steps
+        line["mixed_vs_fp64_error"] = {
+            "steps": mixed["t"],
+            "max_rel": field_error_summary(mixed["fields"], fp64["fields"]),
+            "note": "max-norm relative error of the mixed path against the float64 GPU path at 256^3 "
+                    "(the float64 path is pinned to the oracle at these sizes on sampled cells)"}
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

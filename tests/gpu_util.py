@@ -23,20 +23,18 @@ def split(out):
 
 
 def field_errors(gpu, ref):
-    """max_x |F_gpu - F_ref| / scale(F) for every field.  The scale of n,
-    eps, P and U^0 is max_x |F_ref|; the spatial components U^1..U^3 share
-    one scale, the largest |U^j_ref| over x and j, because a component that
-    vanishes in the continuum (the transverse flow of a shock tube, a pure
-    lattice artefact here) would otherwise turn rounding into a large ratio;
-    that scale is at least 1e-3 max|U^0_ref|, so a state at rest (spatial
-    components pure rounding on both sides) is measured against the
-    4-velocity's size."""
+    """max_x |F_gpu - F_ref| / scale(F).  For n, eps and P the scale is
+    max_x |F_ref|.  The 4-velocity is compared as a 4-vector: every
+    component U^0..U^3 against max_{x,mu} |U^mu_ref| (which is max U^0 >= 1),
+    because a spatial component can vanish (a state at rest, the transverse
+    flow of a shock tube, a decayed flow) and a per-component ratio would
+    then measure rounding against nothing."""
     g, r = split(gpu), split(ref)
-    vscale = max(max(np.max(np.abs(r["U%d" % j])) for j in (1, 2, 3)), 1e-3 * np.max(np.abs(r["U0"])))
+    uscale = max(np.max(np.abs(r["U%d" % j])) for j in range(4))
     out = {}
     for k in FIELDS:
-        scale = vscale if k in ("U1", "U2", "U3") else np.max(np.abs(r[k]))
-        out[k] = float(np.max(np.abs(g[k] - r[k])) / scale) if scale > 0 else float(np.max(np.abs(g[k])))
+        scale = uscale if k.startswith("U") else np.max(np.abs(r[k]))
+        out[k] = float(np.max(np.abs(g[k] - r[k])) / scale)
     return out
 
 

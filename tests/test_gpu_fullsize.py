@@ -1,0 +1,66 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py
+times, on sampled cells the oracle can compute one by one: after k steps a
+cell depends only on cells within 6k (the largest displacement is 6), so the
+oracle runs a periodic (12k+1)^3 window of the initial fields centred on the
+sample and its centre cell is exact.  Samples include the box corners, so
+the periodic wrap is exercised."""
+import numpy as np
+import pytest
+
+from gpu_util import note
+from oracle import rlb as orlb
+from paper_1301_3423_amd import inputs, rlb
+
+pytestmark = pytest.mark.gpu
+
+K = 2                      # steps
+W = 12 * K + 1             # window edge
+
+
+def _window(a, c):
+    """Periodic window of edge W centred on cell c = (z, y, x)."""
+    idx = [np.arange(ci - 6 * K, ci + 6 * K + 1) % n for ci, n in zip(c, a.shape)]
+    return a[np.ix_(*idx)]
+
+
+def _samples(edge, rng, count=6):
+    pts = [(0, 0, 0), (edge - 1, edge - 1, edge - 1), (edge // 2, 0, edge - 1)]
+    while len(pts) < count:
+        pts.append(tuple(int(v) for v in rng.integers(0, edge, 3)))
+    return pts
+
+
+@pytest.mark.parametrize("edge,precision,vmax,eta_s,seed", [
+    (128, "fp64", 0.5, 0.2, 2),     # the 128^3 float64 configuration
+    (256, "fp64", 0.6, 0.5, 3),     # 256^3 float64 (timed next to the mixed one)
+    (256, "mixed", 0.6, 0.5, 3),    # the 256^3 mixed configuration
+])
+def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed):
+    note("full size %d^3 %s, %d steps" % (edge, precision, K))
+    fields = inputs.random_box(edge, edge, edge, vmax, seed)
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
+    s.init_fields(*fields)
+    s.step(K)
+    out = s.read_fields()
+    flags, _ = s.status()
+    assert flags == 0
+    del s
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    rng = np.random.default_rng(edge)
+    worst = 0.0
+    for c in _samples(edge, rng):
+        win = [_window(a, c) for a in fields]
+        o = orlb.Solver(W, W, W, lat=lat, eta_s=eta_s)
+        o.init_fields(*win)
+        o.step(K)
+        ref = o.read_fields()
+        mid = (6 * K) * W * W + (6 * K) * W + 6 * K
+        flat = c[0] * edge * edge + c[1] * edge + c[2]
+        U0 = ref["U"][0, mid]
+        errs = [abs(out["n"][flat] - ref["n"][mid]) / ref["n"][mid],
+                abs(out["eps"][flat] - ref["eps"][mid]) / ref["eps"][mid],
+                abs(out["P"][flat] - ref["P"][mid]) / ref["P"][mid]] + \
+               [abs(out["U"][j, flat] - ref["U"][j, mid]) / U0 for j in range(4)]
+        worst = max(worst, max(errs))
+        assert max(errs) <= tol, (c, errs)
+    note("worst sampled relative error %.2e" % worst)
