@@ -22,10 +22,13 @@ __device__ __forceinline__ S load_at(const S *base, int cell) {
   return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + boff);
 }
 
+// Post-collision values are not read again before the whole lattice has
+// streamed through the caches, so they are stored non-temporally (measured
+// +2-3 % on the step kernels; non-temporal loads were slower).
 template <class S>
 __device__ __forceinline__ void store_at(S *base, int cell, S v) {
   const uint32_t boff = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
-  *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + boff) = v;
+  __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(base) + boff));
 }
 
 __device__ __forceinline__ void cell_coords(int cell, const Geom &g, int &x, int &y, int &z) {
