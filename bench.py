@@ -240,6 +240,32 @@ def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
     }
 
 
+def run_riemann():
+    """Latency of the 1D Riemann problems: the 1x1x200 tube (T 1.0 | 0.8,
+    eta/s 0.1, 200 steps, FP64) and the paper's 1x1x1600 tube (T 1.0 | 0.5,
+    eta/s 0.5, 63 steps), each as one persistent launch, wall time from
+    submission of the launch to fields on the host."""
+    import torch
+    from paper_1301_3423_amd import inputs, rlb
+    out = {}
+    for name, n, tl, tr, es, steps in (("tube_200", 200, 1.0, 0.8, 0.1, 200),
+                                       ("paper_1600", 1600, 1.0, 0.5, 0.5, 63)):
+        b = rlb.Batch([dict(n=n, eta_s=es)], precision="fp64")
+        f = inputs.shock_tube(n, tl, tr)
+        b.init_tube(0, *f)
+        b.step(2)
+        b.init_tube(0, *f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        r = b.read_tube(0)
+        dt = time.perf_counter() - t0
+        out[name] = {"cells": n, "steps": steps, "wall_ms": round(dt * 1e3, 3),
+                     "max_vz": round(float(np.max(np.abs(r["U"][3] / r["U"][0]))), 4),
+                     "flags": b.status(0)[0]}
+    return out
+
+
 def cpu_baseline(vmax, eta_s):
     """The FP64 oracle on a bounded sample of the same workload."""
     from threadpoolctl import threadpool_limits
@@ -291,6 +317,7 @@ def main():
             tubes[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "launch_ms": round(r["ms"], 3),
                            "achieved_GBps": round(r["achieved_gbs"], 1), "cells": r["cells"],
                            "tubes_flagged": r["tubes_flagged"]}
+    riemann = run_riemann()
     serving = None
     if args.serve_requests > 0:
         serving = run_serving(args.serve_requests)
@@ -345,6 +372,7 @@ def main():
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",
                          **tubes}
+    line["riemann_fp64"] = riemann
     if serving is not None:
         line["serving"] = serving
     if cpu is not None:
