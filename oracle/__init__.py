@@ -1,5 +1,6 @@
 """Plain FP64 CPU oracle of the third-order relativistic lattice Boltzmann
-scheme (RLBD) of Mendoza, Karlin, Succi and Herrmann.
+scheme (RLBD) of Mendoza, Karlin, Succi and Herrmann, and of the
+second-order model of its Appendix A.
 
 This package is TEST INFRASTRUCTURE.  Only the tests, the smoke check and the
 CPU-baseline leg of the benchmark may import it; the library never does, and
@@ -18,5 +19,5 @@ Modules
   landau       the Landau-Lifshitz eigenproblem (Eq. eigenproblem)
   rlb          moments, collision, exact streaming, the time step (Eq. rlb:disc)
 """
-from .lattice import Lattice, load_lattice, default_table_path  # noqa: F401
+from .lattice import Lattice, load_lattice, model_lattice, default_table_path  # noqa: F401
 from . import basis, equilibrium, landau, rlb  # noqa: F401

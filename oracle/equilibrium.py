@@ -70,7 +70,8 @@ def projections(n, T, U, kmax=30):
 class Equilibrium:
     """Discrete equilibrium on a lattice (Eq. disc1), with J_k(p_i)
     evaluated once.  kmax = 30 is the third-order model; kmax = 14 keeps the
-    polynomials up to second order (Appendix B, Eq. equi2nd)."""
+    polynomials up to second order (Appendix A's model, whose equilibrium
+    Appendix B prints as Eq. equi2nd)."""
 
     def __init__(self, lat, kmax=30):
         self.lat = lat

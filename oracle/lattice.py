@@ -4,8 +4,9 @@ A lattice point i carries an integer spatial displacement theta_i with
 |theta_i|^2 = R^2, an energy p0_i (a zero of the radial polynomial) and a
 weight w_i.  Its 4-momentum is p_i = p0_i (1, theta_i / R) (Eq. mrecon).
 
-The weights themselves sit in the paper's supplement; the table read here
-was recomputed from the paper's conditions (Eqs. eqs:eqs) and is checked
+The weights themselves sit in the paper's supplement; the tables read here
+were recomputed from the paper's conditions (Eqs. eqs:eqs, and the same
+conditions up to second order for the model of Appendix A) and are checked
 against them by the tests.  This module has its own parser and shares no
 code with the library.
 """
@@ -39,6 +40,12 @@ class Lattice:
         # spatial inverse of each point (same energy, opposite theta)
         key = {(int(s), tuple(t)): i for i, (s, t) in enumerate(zip(self.shell, self.theta))}
         self.inv = np.array([key[(int(s), tuple(-t))] for s, t in zip(self.shell, self.theta)])
+
+
+def model_lattice(order=3):
+    """The lattice of the third-order model (order 3: d3q128, R^2 = 41) or
+    of the second-order model of Appendix A (order 2: d3q66, R^2 = 9)."""
+    return load_lattice(default_table_path({3: "d3q128", 2: "d3q66"}[order]))
 
 
 def load_lattice(path=None):

@@ -16,12 +16,24 @@ One step, for every cell x, in the paper's order:
 
 Arrays: populations f[Q, nz, ny, nx] (x fastest), the same ordering the
 library stores on the device.
+
+Two models share these steps: the third-order model (order 3: 128 points,
+R = sqrt(41), J_0..J_29) and the second-order model of Appendix A (order 2:
+66 points, R = 3, J_0..J_13, Eq. equi2nd).  They differ in the lattice, the
+number of Table I polynomials kept, and the viscosity-tau relation.
 """
 import numpy as np
 
 from . import landau
 from .equilibrium import Equilibrium, ETA
-from .lattice import load_lattice
+from .lattice import load_lattice, model_lattice
+
+# shear viscosity eta = n T (tau - 1/2) / (c R): c = 3/2 for the third-order
+# model (Sec. III, eta = (2/3) P (tau - 1/2) / R) and c = 7 for the
+# second-order model (the numerical fit eta_2nd ~ (1/7) P (tau - 1/2) / R of
+# Appendix A); P = n T
+VISCOSITY_C = {3: 1.5, 2: 7.0}
+KMAX = {3: 30, 2: 14}
 
 FLAG_NONFINITE = 1
 FLAG_NONPHYSICAL = 2
@@ -53,23 +65,25 @@ def macroscopic(lat, f2):
     return dict(N=N, Tm=Tm, n=n, eps=eps, T=T, P=eps / 3.0, U=U, iters=iters, flags=flags)
 
 
-def relaxation_time(lat, n, T, tau=None, eta_s=None):
+def relaxation_time(lat, n, T, tau=None, eta_s=None, order=3):
     """Step 4.  Either a fixed tau, or tau from the ratio eta/s per cell:
-    the shear viscosity eta = (2/3) n T (tau - 1/2) / R (Sec. III, with
+    the shear viscosity eta = n T (tau - 1/2) / (c R) (VISCOSITY_C, with
     delta t' = 1) and the entropy density s = 4 n - n ln(n / n_eq) with
     n_eq = T^3 in the numerical units of Sec. III (there n = T^3 at rest,
     P = T^4), which give
-        tau = 1/2 + (3 R / (2 T)) (eta/s) (4 - ln(n / T^3))."""
+        tau = 1/2 + (c R / T) (eta/s) (4 - ln(n / T^3)),
+    i.e. 1/2 + (3 R / (2 T)) (eta/s) (4 - ln(n / T^3)) for the third-order
+    model."""
     if tau is not None:
         return np.full_like(n, float(tau))
-    return 0.5 + (1.5 * lat.R / T) * eta_s * (4.0 - np.log(n / T**3))
+    return 0.5 + (VISCOSITY_C[order] * lat.R / T) * eta_s * (4.0 - np.log(n / T**3))
 
 
-def collide(lat, eq, f2, tau=None, eta_s=None):
+def collide(lat, eq, f2, tau=None, eta_s=None, order=3):
     """Steps 1-6 on f2[Q, C]; returns the post-collision populations and
     the macroscopic state that was used."""
     mac = macroscopic(lat, f2)
-    tau_c = relaxation_time(lat, mac["n"], mac["T"], tau, eta_s)
+    tau_c = relaxation_time(lat, mac["n"], mac["T"], tau, eta_s, order)
     feq = eq(mac["n"], mac["T"], mac["U"]).T                     # [Q, C]
     U = mac["U"]
     # p_i^mu U_mu / p_i^0 = U^0 - (theta_i / R) . U_vec
@@ -99,13 +113,17 @@ def equilibrium_state(eq, n, eps, vx, vy, vz):
 
 
 class Solver:
-    """A periodic nx x ny x nz lattice advanced by Eq. rlb:disc."""
+    """A periodic nx x ny x nz lattice advanced by Eq. rlb:disc, with the
+    third-order (order=3) or the second-order (order=2) model."""
 
-    def __init__(self, nx, ny, nz, tau=None, eta_s=None, lat=None, kmax=30):
+    def __init__(self, nx, ny, nz, tau=None, eta_s=None, lat=None, kmax=None, order=3):
         if (tau is None) == (eta_s is None):
             raise ValueError("give exactly one of tau, eta_s")
-        self.lat = lat or load_lattice()
-        self.eq = Equilibrium(self.lat, kmax)
+        if order not in KMAX:
+            raise ValueError("order must be 2 or 3")
+        self.order = order
+        self.lat = lat or model_lattice(order)
+        self.eq = Equilibrium(self.lat, KMAX[order] if kmax is None else kmax)
         self.shape = (nz, ny, nx)
         self.C = nx * ny * nz
         self.tau, self.eta_s = tau, eta_s
@@ -121,7 +139,7 @@ class Solver:
     def step(self, nsteps=1):
         for _ in range(nsteps):
             f2 = self.f.reshape(self.lat.Q, self.C)
-            fs, mac = collide(self.lat, self.eq, f2, self.tau, self.eta_s)
+            fs, mac = collide(self.lat, self.eq, f2, self.tau, self.eta_s, self.order)
             self.flags |= mac["flags"]
             self.f = stream(self.lat, fs.reshape(self.f.shape))
             self.t += 1

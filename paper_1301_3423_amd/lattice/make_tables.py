@@ -278,7 +278,8 @@ def write_tables(name, r2, nshell, maxdeg, vertex, note):
 def search(name, r2, nshell, maxdeg, nseed, want_points):
     """Vertices for seeds 0..nseed-1; keep those with the wanted number of
     points whose polished weights meet every condition to 1e-13, and return
-    the one with the largest smallest weight (the best-conditioned choice)."""
+    the one with the largest smallest weight (the best-conditioned choice).
+    want_points = None keeps the sparsest vertices instead (fewest points)."""
     best = None
     for seed in range(nseed):
         v = build_vertex(r2, nshell, maxdeg, seed)
@@ -290,15 +291,25 @@ def search(name, r2, nshell, maxdeg, nseed, want_points):
             [float(p['w']) for p in pts], maxdeg)
         wmin = min(float(p['w']) for p in pts)
         print("seed %3d  points %3d  resid %.1e  min w %.3e" % (seed, len(pts), res, wmin), flush=True)
-        if res > 1e-13 or len(pts) != want_points:
+        if res > 1e-13 or (want_points is not None and len(pts) != want_points):
             continue
-        if best is None or wmin > best[0]:
-            best = (wmin, v)
+        key = (-len(pts), wmin)
+        if best is None or key > best[0]:
+            best = (key, v)
     return best[1]
 
 
 if __name__ == "__main__":
-    nseed = int(sys.argv[1]) if len(sys.argv) > 1 else 64
-    v3 = search("d3q128", 41, 4, 6, nseed, 128)
-    print(write_tables("d3q128", 41, 4, 6, v3,
-                       "third-order model (R = sqrt(41), degree <= 6)"))
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if which in ("all", "d3q128"):
+        # third order (Sec. II C): R^2 = 41, zeros of R^(4), degree <= 6, 128 points
+        v3 = search("d3q128", 41, 4, 6, 64, 128)
+        print(write_tables("d3q128", 41, 4, 6, v3,
+                           "third-order model (R = sqrt(41), degree <= 6)"))
+    if which in ("all", "d3q66"):
+        # second order (Appendix A): R^2 = 9, zeros of R^(3); three shells make
+        # the radial rule exact to degree 5, so the conditions are taken to
+        # degree 5; the sparsest vertices have the paper's 66 points
+        v2 = search("d3q66", 9, 3, 5, 64, None)
+        print(write_tables("d3q66", 9, 3, 5, v2,
+                           "second-order model (R = 3, degree <= 5, sparsest vertex)"))

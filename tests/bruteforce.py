@@ -1,13 +1,14 @@
 """A second, deliberately naive implementation of one step of Eq. rlb:disc
 for tiny lattices: pure-Python loops over cells and populations, LAPACK's
-eigen-solver for the Landau-Lifshitz frame and the closed-form equilibrium
-of Appendix B (Eq. equi3rd).  It shares nothing with the oracle except the
-lattice table, and exists to pin the oracle on small cases."""
+eigen-solver for the Landau-Lifshitz frame and the closed-form equilibria
+of Appendix B (Eq. equi3rd for the third-order model, Eq. equi2nd for the
+second-order model of Appendix A).  It shares nothing with the oracle
+except the lattice table, and exists to pin the oracle on small cases."""
 import math
 
 import numpy as np
 
-from appendix_equilibrium import equi3rd
+from appendix_equilibrium import equi2nd, equi3rd
 
 ETA = np.diag([1.0, -1.0, -1.0, -1.0])
 
@@ -25,8 +26,14 @@ def landau_eig(Tm):
     raise RuntimeError("no timelike eigenvector")
 
 
-def step(lat, f, shape, tau=None, eta_s=None):
-    """f[Q][nz][ny][nx] (numpy) -> new array after collide + push."""
+def step(lat, f, shape, tau=None, eta_s=None, order=3):
+    """f[Q][nz][ny][nx] (numpy) -> new array after collide + push.
+    eta/s gives tau through eta = (2/3) n T (tau - 1/2) / R (Sec. III) for
+    the third-order model and eta = (1/7) n T (tau - 1/2) / R (Appendix A)
+    for the second-order one."""
+    equi = equi3rd if order == 3 else equi2nd
+    # tau - 1/2 = eta / (k n T / R) = (R / (k T)) (eta/s) (s/n)
+    k = 2.0 / 3.0 if order == 3 else 1.0 / 7.0
     nz, ny, nx = shape
     Q = lat.Q
     out = np.zeros_like(f)
@@ -45,9 +52,9 @@ def step(lat, f, shape, tau=None, eta_s=None):
                 if tau is not None:
                     t = tau
                 else:
-                    t = 0.5 + 1.5 * lat.R / T * eta_s * (4 - math.log(n / T**3))
+                    t = 0.5 + lat.R / (k * T) * eta_s * (4 - math.log(n / T**3))
                 for i in range(Q):
-                    feq = equi3rd(n, T, U, lat.p[i], lat.w[i])
+                    feq = equi(n, T, U, lat.p[i], lat.w[i])
                     pU = lat.p[i] @ ETA @ U
                     fs = fc[i] - pU / (t * lat.p[i, 0]) * (fc[i] - feq)
                     tx, ty, tz = (int(a) for a in lat.theta[i])
