@@ -1,21 +1,24 @@
 /*
  * rlb.h -- C ABI of the MI355X library for the third-order relativistic
  * lattice Boltzmann scheme (RLBD) of Mendoza, Karlin, Succi and Herrmann,
- * "Relativistic Lattice Boltzmann Model with Improved Dissipation".
+ * "Relativistic Lattice Boltzmann Model with Improved Dissipation", and of
+ * the second-order model of its Appendix A.
  *
  * What one step computes (Sec. II D, Eq. rlb:disc, time step delta t' = 1):
  *
  *   f_i(x + theta_i, t + 1) = f_i(x, t)
  *                             - (p_i^mu U_mu / (tau p_i^0)) (f_i - f_i^eq)
  *
- * on a periodic nx x ny x nz cubic lattice, with 128 discrete 4-momenta
- * p_i = p0_i (1, theta_i / R), R = sqrt(41) (Sec. II C, Eqs. dio, mrecon2).
- * Per cell: the moments N^mu = sum f_i p_i^mu and T^{mu nu} =
- * sum f_i p_i^mu p_i^nu; the Landau-Lifshitz eigenproblem
- * T^{mu nu} U_nu = eps U^mu (Eq. eigenproblem); n = U_mu N^mu; the equation
- * of state eps = 3 n T, P = eps / 3; the Maxwell-Juttner equilibrium
- * projected on the orthonormal polynomials of Table I up to third order
- * (Eqs. coeff, disc1); and the Anderson-Witting relaxation.
+ * on a periodic nx x ny x nz cubic lattice, with discrete 4-momenta
+ * p_i = p0_i (1, theta_i / R): 128 of them with R = sqrt(41) for the
+ * third-order model (Sec. II C, Eqs. dio, mrecon2), 66 with R = 3 for the
+ * second-order model (Appendix A).  Per cell: the moments
+ * N^mu = sum f_i p_i^mu and T^{mu nu} = sum f_i p_i^mu p_i^nu; the
+ * Landau-Lifshitz eigenproblem T^{mu nu} U_nu = eps U^mu
+ * (Eq. eigenproblem); n = U_mu N^mu; the equation of state eps = 3 n T,
+ * P = eps / 3; the Maxwell-Juttner equilibrium projected on the orthonormal
+ * polynomials of Table I up to third order (Eqs. coeff, disc1, equi3rd) or
+ * up to second order (Eq. equi2nd); and the Anderson-Witting relaxation.
  *
  * Conventions
  *  - Every call returns RLB_OK (0) or a negative error code; no C++
@@ -59,13 +62,21 @@ extern "C" {
                        coefficients in float64; equilibrium and relaxation of
                        each population in float32                            */
 
+/* ---- model ----------------------------------------------------------------
+ * The `order` argument or field selects the model; 0 means the default,
+ * RLB_ORDER3.  Any other value is RLB_EINVAL. */
+#define RLB_ORDER3 3 /* third-order model: 128 points, R^2 = 41, 4 shells */
+#define RLB_ORDER2 2 /* second-order model: 66 points, R^2 = 9, 3 shells  */
+
 /* ---- relaxation time ---------------------------------------------------- */
 #define RLB_TAU_FIXED 0 /* tau is a constant (> 1/2)                         */
 #define RLB_TAU_ETA_S 1 /* tau per cell and step from eta/s:
-                           eta = (2/3) n T (tau - 1/2) / R and
+                           eta = n T (tau - 1/2) / (c R) and
                            s = 4 n - n ln(n / n_eq) with n_eq = T^3
                            (Sec. II D transport coefficients, Sec. III), i.e.
-                           tau = 1/2 + (3R/(2T)) (eta/s) (4 - ln(n/T^3))     */
+                           tau = 1/2 + (c R / T) (eta/s) (4 - ln(n/T^3)),
+                           c = 3/2 for the third-order model and c = 7 for
+                           the second-order one (the fit of Appendix A)     */
 
 /* ---- status flags (sticky, OR-ed by the kernels) ----------------------- */
 #define RLB_FLAG_NONFINITE 1u   /* a cell produced a NaN or infinity        */
@@ -74,13 +85,16 @@ extern "C" {
 
 #define RLB_MAX_Q 128
 
-/* The discrete velocity set: 128 points on 4 energy shells (Sec. II C).
+/* The discrete velocity set of a model: q points (128 on 4 energy shells
+ * for the third-order model, Sec. II C; 66 on 3 shells for the second-order
+ * one, Appendix A); entries beyond q are zero.
  * theta: integer displacement per step; p0: energy; w: weight;
  * inv[i]: index of the point with theta = -theta_i on the same shell (the
- * library orders points so that inv[i] == i ^ 1); shell: 0..3.  The weights
- * were recomputed from the paper's conditions (Eqs. eqs:eqs) because the
- * paper lists them only in a supplement; sha256 is that of the text table
- * they come from. */
+ * library orders points so that inv[i] == i ^ 1); shell: 0..nshell-1.  The
+ * weights were recomputed from the paper's conditions (Eqs. eqs:eqs, for
+ * polynomials up to degree 6 in the third-order model and 5 in the
+ * second-order one) because the paper lists them only in a supplement;
+ * sha256 is that of the text table they come from. */
 typedef struct rlb_lattice {
   int32_t q;
   int32_t r2;
@@ -93,8 +107,9 @@ typedef struct rlb_lattice {
   char sha256[65];
 } rlb_lattice_t;
 
-/* Fills *out with the library's lattice.  Read-only library data. */
-int rlb_lattice_info(rlb_lattice_t *out);
+/* Fills *out with the lattice of model `order` (0, RLB_ORDER2 or
+ * RLB_ORDER3).  Read-only library data; RLB_EINVAL for NULL or a bad order. */
+int rlb_lattice_info(int32_t order, rlb_lattice_t *out);
 
 /* ---- one periodic box ---------------------------------------------------- */
 typedef struct rlb_config {
@@ -103,14 +118,16 @@ typedef struct rlb_config {
   int32_t tau_mode;   /* RLB_TAU_FIXED or RLB_TAU_ETA_S                   */
   double tau;         /* relaxation time when tau_mode == RLB_TAU_FIXED   */
   double eta_s;       /* eta/s (> 0) when tau_mode == RLB_TAU_ETA_S        */
+  int32_t order;      /* model: 0 or RLB_ORDER3, or RLB_ORDER2             */
 } rlb_config;
 
 typedef struct rlb_solver rlb_solver;
 
-/* Bytes of device memory a box of this size needs: two population buffers
- * (the kernels read one and write the other) plus a 4 KiB status area.
- * Returns 0 for invalid sizes or precision.  Pure function. */
-size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision);
+/* Bytes of device memory a box of this size and model needs: two
+ * population buffers (the kernels read one and write the other) plus a
+ * 4 KiB status area.  Returns 0 for invalid sizes, precision or order.
+ * Pure function. */
+size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order);
 
 /* Creates a solver over caller-owned device memory d_buf of `bytes` bytes
  * (>= rlb_state_bytes, 256-byte aligned) on `stream` of the current device.
@@ -183,14 +200,15 @@ typedef struct rlb_tube {
 
 typedef struct rlb_batch rlb_batch;
 
-/* Device bytes for a batch of these tubes (0 if any tube is invalid). */
-size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision);
+/* Device bytes for a batch of these tubes under model `order` (0 if any
+ * tube, the precision or the order is invalid). */
+size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision, int32_t order);
 
-/* Creates a batch over caller-owned device memory (>= rlb_batch_bytes,
- * 256-byte aligned) on `stream`.  The tube array is copied.  Errors as for
- * rlb_create. */
-int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, void *d_buf,
-                     size_t bytes, void *stream);
+/* Creates a batch of one precision and one model over caller-owned device
+ * memory (>= rlb_batch_bytes, 256-byte aligned) on `stream`.  The tube array
+ * is copied.  Errors as for rlb_create. */
+int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, int32_t order,
+                     void *d_buf, size_t bytes, void *stream);
 
 /* Initial fields of one tube (n values each, index = z); semantics and
  * errors as rlb_init_fields.  Resets that tube's t and flags. */
@@ -220,7 +238,7 @@ void rlb_batch_destroy(rlb_batch *b);
  * the pool, and advances everything resident in rounds: each box by
  * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), each
  * tube by max(chunk_steps, chunk_steps * 4096 / nz) steps, all resident
- * tubes of one precision in one persistent launch.  Finished
+ * tubes of one precision and model in one persistent launch.  Finished
  * requests are read back, their memory is freed and they are reported by
  * rlb_server_poll.  A request's result does not depend on what else is
  * resident (the kernels never mix requests).  Times are seconds since the
@@ -233,6 +251,7 @@ typedef struct rlb_request {
   int32_t nx, ny, nz; /* lattice size (a tube has nx = ny = 1)                */
   int32_t precision;  /* RLB_FP64 or RLB_MIXED                                */
   int32_t tau_mode;   /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */
+  int32_t order;      /* model: 0 or RLB_ORDER3, or RLB_ORDER2                */
   double tau, eta_s;
   int64_t steps;      /* >= 0                                                  */
   /* initial fields, nx*ny*nz host values each; copied by rlb_server_submit  */

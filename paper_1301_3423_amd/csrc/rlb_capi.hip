@@ -44,6 +44,18 @@ int64_t pop_stride(int64_t cells, int precision) {
   return (cells + per - 1) / per * per + per;
 }
 
+// order 0 selects the default, the third-order model
+bool valid_order(int32_t o) { return o == 0 || o == RLB_ORDER2 || o == RLB_ORDER3; }
+int norm_order(int32_t o) { return o == 0 ? RLB_ORDER3 : o; }
+int q_of(int order) { return order == RLB_ORDER2 ? rlb::M2::Q : rlb::M3::Q; }
+
+// Calls f with a value of the model type of `order` (normalised: 2 or 3).
+template <class F>
+decltype(auto) with_model(int order, F &&f) {
+  if (order == RLB_ORDER2) return f(rlb::M2{});
+  return f(rlb::M3{});
+}
+
 bool valid_dims(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   const int64_t c = static_cast<int64_t>(nx) * ny * nz;
@@ -92,27 +104,30 @@ rlb::Relax relax_of(const rlb_solver *s) {
 
 unsigned grid_of(int64_t cells) { return static_cast<unsigned>((cells + rlb::BLOCK - 1) / rlb::BLOCK); }
 
+// float64: the two-lane kernel; float32: one lane per cell when rows are
+// whole wavefronts (nx % 64 == 0), else the two-lane kernel.
 int launch_step(rlb_solver *s) {
   const rlb::Geom g = geom_of(s);
   const rlb::Relax r = relax_of(s);
-  if (s->cfg.precision == RLB_FP64) {
-    constexpr int TB = rlb::pair_block<double>;
-    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-    hipLaunchKernelGGL(rlb::k_step<double>, grid, block, 0, s->stream,
-                       static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r,
-                       s->status);
-  } else if (s->cfg.nx % 64 == 0) {
-    const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
-    hipLaunchKernelGGL(rlb::k_step_row<float>, grid, block, 0, s->stream,
-                       static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r,
-                       s->status);
-  } else {
-    constexpr int TB = rlb::pair_block<float>;
-    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-    hipLaunchKernelGGL(rlb::k_step<float>, grid, block, 0, s->stream,
-                       static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r,
-                       s->status);
-  }
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    if (s->cfg.precision == RLB_FP64) {
+      constexpr int TB = rlb::pair_block<double>;
+      const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
+      rlb::k_step<M, double><<<grid, block, 0, s->stream>>>(static_cast<const double *>(s->buf[s->cur]),
+                                                            static_cast<double *>(s->buf[1 - s->cur]), g, r, s->status);
+    } else if (s->cfg.nx % 64 == 0) {
+      const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
+      rlb::k_step_row<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]),
+                                                               static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status);
+    } else {
+      constexpr int TB = rlb::pair_block<float>;
+      const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
+      rlb::k_step<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]),
+                                                           static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status);
+    }
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_step launch");
   s->cur = 1 - s->cur;
@@ -145,33 +160,42 @@ const char *rlb_strerror(int code) {
   }
 }
 
-int rlb_lattice_info(rlb_lattice_t *out) {
+int rlb_lattice_info(int32_t order, rlb_lattice_t *out) {
   if (!out) return fail(RLB_EINVAL, "rlb_lattice_info: NULL");
+  if (!valid_order(order)) return fail(RLB_EINVAL, "rlb_lattice_info: order must be 0, 2 or 3");
+  order = norm_order(order);
   std::memset(out, 0, sizeof(*out));
-  out->q = rlb::Q;
-  out->r2 = rlb::R2;
-  out->nshell = rlb::NSHELL;
-  for (int i = 0; i < rlb::Q; ++i) {
-    const rlb::Point &p = rlb::D3Q128[i];
-    out->theta[i][0] = static_cast<int8_t>(p.tx);
-    out->theta[i][1] = static_cast<int8_t>(p.ty);
-    out->theta[i][2] = static_cast<int8_t>(p.tz);
-    out->p0[i] = p.p0;
-    out->w[i] = p.w;
-    out->inv[i] = i ^ 1;
-    out->shell[i] = p.shell;
-  }
-  static const char kSha[] =
+  static const char kSha3[] =
 #include "../lattice/d3q128.sha"
       ;
-  std::snprintf(out->sha256, sizeof(out->sha256), "%s", kSha);
-  return RLB_OK;
+  static const char kSha2[] =
+#include "../lattice/d3q66.sha"
+      ;
+  return with_model(order, [&](auto m) {
+    using M = decltype(m);
+    out->q = M::Q;
+    out->r2 = M::R2;
+    out->nshell = M::NSHELL;
+    for (int i = 0; i < M::Q; ++i) {
+      const rlb::Point &p = M::P[i];
+      out->theta[i][0] = static_cast<int8_t>(p.tx);
+      out->theta[i][1] = static_cast<int8_t>(p.ty);
+      out->theta[i][2] = static_cast<int8_t>(p.tz);
+      out->p0[i] = p.p0;
+      out->w[i] = p.w;
+      out->inv[i] = i ^ 1;
+      out->shell[i] = p.shell;
+    }
+    std::snprintf(out->sha256, sizeof(out->sha256), "%s", M::ORDER == 2 ? kSha2 : kSha3);
+    return RLB_OK;
+  });
 }
 
-size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision) {
-  if (!valid_dims(nx, ny, nz) || (precision != RLB_FP64 && precision != RLB_MIXED)) return 0;
+size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order) {
+  if (!valid_dims(nx, ny, nz) || (precision != RLB_FP64 && precision != RLB_MIXED) || !valid_order(order)) return 0;
   const int64_t cells = static_cast<int64_t>(nx) * ny * nz;
-  const size_t buf = static_cast<size_t>(rlb::Q) * pop_stride(cells, precision) * elem_bytes(precision);
+  const size_t buf =
+      static_cast<size_t>(q_of(norm_order(order))) * pop_stride(cells, precision) * elem_bytes(precision);
   return 2 * buf + STATUS_BYTES;
 }
 
@@ -181,6 +205,7 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
   if (!valid_dims(cfg->nx, cfg->ny, cfg->nz)) return fail(RLB_EINVAL, "rlb_create: bad lattice size");
   if (cfg->precision != RLB_FP64 && cfg->precision != RLB_MIXED)
     return fail(RLB_EINVAL, "rlb_create: bad precision");
+  if (!valid_order(cfg->order)) return fail(RLB_EINVAL, "rlb_create: order must be 0, 2 or 3");
   if (cfg->tau_mode == RLB_TAU_FIXED) {
     if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) return fail(RLB_EINVAL, "rlb_create: tau must exceed 1/2");
   } else if (cfg->tau_mode == RLB_TAU_ETA_S) {
@@ -189,7 +214,7 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
     return fail(RLB_EINVAL, "rlb_create: bad tau_mode");
   }
   if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_create: buffer not 256-byte aligned");
-  const size_t need = rlb_state_bytes(cfg->nx, cfg->ny, cfg->nz, cfg->precision);
+  const size_t need = rlb_state_bytes(cfg->nx, cfg->ny, cfg->nz, cfg->precision, cfg->order);
   if (bytes < need)
     return fail(RLB_ENOMEM, "rlb_create: buffer has " + std::to_string(bytes) + " bytes, needs " + std::to_string(need));
   int dev = 0;
@@ -197,13 +222,14 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
   rlb_solver *s = new (std::nothrow) rlb_solver();
   if (!s) return fail(RLB_EINVAL, "rlb_create: out of host memory");
   s->cfg = *cfg;
+  s->cfg.order = norm_order(cfg->order);
   s->device = dev;
   s->stream = static_cast<hipStream_t>(stream);
   s->base = static_cast<char *>(d_buf);
   s->bytes = bytes;
   s->cells = static_cast<int64_t>(cfg->nx) * cfg->ny * cfg->nz;
   s->stride = pop_stride(s->cells, cfg->precision);
-  s->buf_bytes = static_cast<size_t>(rlb::Q) * s->stride * elem_bytes(cfg->precision);
+  s->buf_bytes = static_cast<size_t>(q_of(s->cfg.order)) * s->stride * elem_bytes(cfg->precision);
   s->buf[0] = s->base;
   s->buf[1] = s->base + s->buf_bytes;
   s->status = reinterpret_cast<unsigned *>(s->base + 2 * s->buf_bytes);
@@ -220,7 +246,7 @@ int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const dou
   const int64_t C = s->cells;
   const double *dn = n, *de = eps, *dx = vx, *dy = vy, *dz = vz;
   // the idle buffer doubles as staging for host input (5 C doubles fit in
-  // 128 C values of either precision)
+  // 66 C values of either precision)
   double *stage = static_cast<double *>(s->buf[1 - s->cur]);
   if (!on_device) {
     const double *arrs[5] = {n, eps, vx, vy, vz};
@@ -242,12 +268,16 @@ int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const dou
   RLB_HIP(hipMemsetAsync(s->status, 0, sizeof(unsigned), s->stream));
   const rlb::Geom g = geom_of(s);
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
-  if (s->cfg.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_init<double>, grid, block, 0, s->stream, dn, de, dx, dy, dz,
-                       static_cast<double *>(s->buf[s->cur]), g, s->status);
-  else
-    hipLaunchKernelGGL(rlb::k_init<float>, grid, block, 0, s->stream, dn, de, dx, dy, dz,
-                       static_cast<float *>(s->buf[s->cur]), g, s->status);
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    if (s->cfg.precision == RLB_FP64)
+      rlb::k_init<M, double><<<grid, block, 0, s->stream>>>(dn, de, dx, dy, dz, static_cast<double *>(s->buf[s->cur]),
+                                                            g, s->status);
+    else
+      rlb::k_init<M, float><<<grid, block, 0, s->stream>>>(dn, de, dx, dy, dz, static_cast<float *>(s->buf[s->cur]),
+                                                           g, s->status);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_init launch");
   if (!on_device) RLB_HIP(hipStreamSynchronize(s->stream));
@@ -281,12 +311,16 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
   }
   const rlb::Geom g = geom_of(s);
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
-  if (s->cfg.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_read<double>, grid, block, 0, s->stream, static_cast<const double *>(s->buf[s->cur]),
-                       g, dn, de, dU, dP, s->status);
-  else
-    hipLaunchKernelGGL(rlb::k_read<float>, grid, block, 0, s->stream, static_cast<const float *>(s->buf[s->cur]),
-                       g, dn, de, dU, dP, s->status);
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    if (s->cfg.precision == RLB_FP64)
+      rlb::k_read<M, double><<<grid, block, 0, s->stream>>>(static_cast<const double *>(s->buf[s->cur]), g, dn, de, dU,
+                                                            dP, s->status);
+    else
+      rlb::k_read<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]), g, dn, de, dU,
+                                                           dP, s->status);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_read launch");
   if (!on_device) {
@@ -305,28 +339,33 @@ int rlb_conserved(rlb_solver *s, double out[5]) {
   const rlb::Geom g = geom_of(s);
   const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
   const int nblocks = static_cast<int>((s->cells + chunk - 1) / chunk);
+  const int Q = q_of(s->cfg.order);
   double *partial = static_cast<double *>(s->buf[1 - s->cur]);
-  double *total = partial + static_cast<size_t>(rlb::Q) * nblocks;
-  const dim3 grid1(nblocks, rlb::Q), block(rlb::BLOCK);
+  double *total = partial + static_cast<size_t>(Q) * nblocks;
+  const dim3 grid1(nblocks, Q), block(rlb::BLOCK);
   if (s->cfg.precision == RLB_FP64)
     hipLaunchKernelGGL(rlb::k_popsum_partial<double>, grid1, block, 0, s->stream,
                        static_cast<const double *>(s->buf[s->cur]), g, partial, nblocks);
   else
     hipLaunchKernelGGL(rlb::k_popsum_partial<float>, grid1, block, 0, s->stream,
                        static_cast<const float *>(s->buf[s->cur]), g, partial, nblocks);
-  hipLaunchKernelGGL(rlb::k_popsum_final, dim3(rlb::Q), block, 0, s->stream, partial, nblocks, total);
+  hipLaunchKernelGGL(rlb::k_popsum_final, dim3(Q), block, 0, s->stream, partial, nblocks, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_popsum launch");
-  double tot[rlb::Q];
-  RLB_HIP(hipMemcpyAsync(tot, total, sizeof(tot), hipMemcpyDeviceToHost, s->stream));
+  double tot[RLB_MAX_Q];
+  RLB_HIP(hipMemcpyAsync(tot, total, Q * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
   for (int k = 0; k < 5; ++k) out[k] = 0.0;
-  for (int i = 0; i < rlb::Q; ++i) {
-    const rlb::Point &p = rlb::D3Q128[i];
-    const double pm[4] = {p.p0, p.p0 * p.tx * rlb::INV_R, p.p0 * p.ty * rlb::INV_R, p.p0 * p.tz * rlb::INV_R};
-    out[0] += p.p0 * tot[i];
-    for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i];
-  }
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    for (int i = 0; i < M::Q; ++i) {
+      const rlb::Point &p = M::P[i];
+      const double pm[4] = {p.p0, p.p0 * p.tx * M::INV_R, p.p0 * p.ty * M::INV_R, p.p0 * p.tz * M::INV_R};
+      out[0] += p.p0 * tot[i];
+      for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i];
+    }
+    return 0;
+  });
   return RLB_OK;
 }
 
@@ -343,6 +382,8 @@ int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t) {
 }
 
 namespace {
+// version 2: the configuration carries the model order
+constexpr int32_t CKPT_VERSION = 2;
 struct CkptHeader {
   char magic[8];
   int32_t version;
@@ -359,20 +400,20 @@ int rlb_save(rlb_solver *s, const char *path) {
   if (!s->initialized) return fail(RLB_ESTATE, "rlb_save: nothing to save");
   CkptHeader h{};
   std::memcpy(h.magic, "RLBCKPT1", 8);
-  h.version = 1;
+  h.version = CKPT_VERSION;
   h.cfg = s->cfg;
   h.t = s->t;
-  h.q = rlb::Q;
+  h.q = q_of(s->cfg.order);
   rlb_lattice_t lat;
-  rlb_lattice_info(&lat);
+  rlb_lattice_info(s->cfg.order, &lat);
   std::memcpy(h.sha256, lat.sha256, sizeof(h.sha256));
   uint32_t flags = 0;
   int rc = rlb_status(s, &flags, nullptr);
   if (rc != RLB_OK) return rc;
   h.flags = flags;
   const size_t eb = elem_bytes(s->cfg.precision);
-  std::vector<char> host(static_cast<size_t>(rlb::Q) * s->cells * eb);
-  RLB_HIP(hipMemcpy2DAsync(host.data(), s->cells * eb, s->buf[s->cur], s->stride * eb, s->cells * eb, rlb::Q,
+  std::vector<char> host(static_cast<size_t>(h.q) * s->cells * eb);
+  RLB_HIP(hipMemcpy2DAsync(host.data(), s->cells * eb, s->buf[s->cur], s->stride * eb, s->cells * eb, h.q,
                            hipMemcpyDeviceToHost, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
   FILE *fp = std::fopen(path, "wb");
@@ -393,20 +434,21 @@ int rlb_load(rlb_solver *s, const char *path) {
     return fail(RLB_EIO, "rlb_load: short header");
   }
   rlb_lattice_t lat;
-  rlb_lattice_info(&lat);
-  if (std::memcmp(h.magic, "RLBCKPT1", 8) != 0 || h.version != 1 || h.q != rlb::Q ||
+  rlb_lattice_info(s->cfg.order, &lat);
+  const int Q = q_of(s->cfg.order);
+  if (std::memcmp(h.magic, "RLBCKPT1", 8) != 0 || h.version != CKPT_VERSION || h.q != Q ||
       std::memcmp(h.sha256, lat.sha256, 64) != 0 || h.cfg.nx != s->cfg.nx || h.cfg.ny != s->cfg.ny ||
       h.cfg.nz != s->cfg.nz || h.cfg.precision != s->cfg.precision || h.cfg.tau_mode != s->cfg.tau_mode ||
-      h.cfg.tau != s->cfg.tau || h.cfg.eta_s != s->cfg.eta_s) {
+      h.cfg.tau != s->cfg.tau || h.cfg.eta_s != s->cfg.eta_s || h.cfg.order != s->cfg.order) {
     std::fclose(fp);
     return fail(RLB_EINVAL, "rlb_load: checkpoint does not match this solver");
   }
   const size_t eb = elem_bytes(s->cfg.precision);
-  std::vector<char> host(static_cast<size_t>(rlb::Q) * s->cells * eb);
+  std::vector<char> host(static_cast<size_t>(Q) * s->cells * eb);
   const bool ok = std::fread(host.data(), 1, host.size(), fp) == host.size();
   std::fclose(fp);
   if (!ok) return fail(RLB_EIO, "rlb_load: short data");
-  RLB_HIP(hipMemcpy2DAsync(s->buf[s->cur], s->stride * eb, host.data(), s->cells * eb, s->cells * eb, rlb::Q,
+  RLB_HIP(hipMemcpy2DAsync(s->buf[s->cur], s->stride * eb, host.data(), s->cells * eb, s->cells * eb, Q,
                            hipMemcpyHostToDevice, s->stream));
   RLB_HIP(hipMemcpyAsync(s->status, &h.flags, sizeof(unsigned), hipMemcpyHostToDevice, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
@@ -421,6 +463,7 @@ int rlb_load(rlb_solver *s, const char *path) {
 
 struct rlb_batch {
   int precision;
+  int order;
   int device;
   hipStream_t stream;
   char *base;
@@ -457,8 +500,8 @@ size_t batch_header_bytes(int ntubes) {
          align256(ntubes * sizeof(unsigned));
 }
 
-size_t tube_buffer_bytes(int32_t n, int precision) {
-  return align256(static_cast<size_t>(rlb::Q) * pop_stride(n, precision) * elem_bytes(precision));
+size_t tube_buffer_bytes(int32_t n, int precision, int order) {
+  return align256(static_cast<size_t>(q_of(order)) * pop_stride(n, precision) * elem_bytes(precision));
 }
 
 rlb::Geom tube_geom(const rlb_batch *b, int j) {
@@ -488,26 +531,28 @@ int wait_staged(rlb_batch *b) {
 
 extern "C" {
 
-size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision) {
-  if (!tubes || ntubes < 1 || (precision != RLB_FP64 && precision != RLB_MIXED)) return 0;
+size_t rlb_batch_bytes(const rlb_tube *tubes, int32_t ntubes, int32_t precision, int32_t order) {
+  if (!tubes || ntubes < 1 || (precision != RLB_FP64 && precision != RLB_MIXED) || !valid_order(order)) return 0;
   size_t total = batch_header_bytes(ntubes);
   for (int j = 0; j < ntubes; ++j) {
     if (!valid_tube(tubes[j])) return 0;
-    total += 2 * tube_buffer_bytes(tubes[j].n, precision);
+    total += 2 * tube_buffer_bytes(tubes[j].n, precision, norm_order(order));
   }
   return total;
 }
 
-int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, void *d_buf,
-                     size_t bytes, void *stream) {
+int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int32_t precision, int32_t order,
+                     void *d_buf, size_t bytes, void *stream) {
   if (!out || !tubes || !d_buf) return fail(RLB_EINVAL, "rlb_batch_create: NULL argument");
   *out = nullptr;
   if (ntubes < 1) return fail(RLB_EINVAL, "rlb_batch_create: no tubes");
   if (precision != RLB_FP64 && precision != RLB_MIXED) return fail(RLB_EINVAL, "rlb_batch_create: bad precision");
+  if (!valid_order(order)) return fail(RLB_EINVAL, "rlb_batch_create: order must be 0, 2 or 3");
+  order = norm_order(order);
   for (int j = 0; j < ntubes; ++j)
     if (!valid_tube(tubes[j])) return fail(RLB_EINVAL, "rlb_batch_create: tube " + std::to_string(j) + " is invalid");
   if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_batch_create: buffer not 256-byte aligned");
-  const size_t need = rlb_batch_bytes(tubes, ntubes, precision);
+  const size_t need = rlb_batch_bytes(tubes, ntubes, precision, order);
   if (bytes < need)
     return fail(RLB_ENOMEM, "rlb_batch_create: buffer has " + std::to_string(bytes) + " bytes, needs " + std::to_string(need));
   int dev = 0;
@@ -515,6 +560,7 @@ int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int
   rlb_batch *b = new (std::nothrow) rlb_batch();
   if (!b) return fail(RLB_EINVAL, "rlb_batch_create: out of host memory");
   b->precision = precision;
+  b->order = order;
   b->device = dev;
   b->stream = static_cast<hipStream_t>(stream);
   b->base = static_cast<char *>(d_buf);
@@ -536,7 +582,7 @@ int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int
   size_t off = 0; // bytes from pops
   for (int j = 0; j < ntubes; ++j) {
     rlb::TubeDesc &d = b->desc[j];
-    const size_t tb = tube_buffer_bytes(tubes[j].n, precision);
+    const size_t tb = tube_buffer_bytes(tubes[j].n, precision, order);
     d.off[0] = static_cast<int64_t>(off / eb);
     d.off[1] = static_cast<int64_t>((off + tb) / eb);
     off += 2 * tb;
@@ -597,12 +643,18 @@ int rlb_batch_init(rlb_batch *b, int32_t tube, const double *n, const double *ep
   RLB_HIP(hipMemsetAsync(b->d_status + tube, 0, sizeof(unsigned), b->stream));
   const rlb::Geom g = tube_geom(b, tube);
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
-  if (b->precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_init<double>, grid, block, 0, b->stream, dn, de, dx, dy, dz,
-                       static_cast<double *>(tube_buf(b, tube, cur)), g, b->d_status + tube);
-  else
-    hipLaunchKernelGGL(rlb::k_init<float>, grid, block, 0, b->stream, dn, de, dx, dy, dz,
-                       static_cast<float *>(tube_buf(b, tube, cur)), g, b->d_status + tube);
+  with_model(b->order, [&](auto m) {
+    using M = decltype(m);
+    if (b->precision == RLB_FP64)
+      rlb::k_init<M, double><<<grid, block, 0, b->stream>>>(dn, de, dx, dy, dz,
+                                                            static_cast<double *>(tube_buf(b, tube, cur)), g,
+                                                            b->d_status + tube);
+    else
+      rlb::k_init<M, float><<<grid, block, 0, b->stream>>>(dn, de, dx, dy, dz,
+                                                           static_cast<float *>(tube_buf(b, tube, cur)), g,
+                                                           b->d_status + tube);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_init launch");
   if (!on_device) RLB_HIP(hipStreamSynchronize(b->stream));
@@ -641,12 +693,16 @@ int rlb_batch_step(rlb_batch *b, const int64_t *steps) {
   RLB_HIP(hipEventRecord(b->staged, b->stream));
   b->staged_pending = true;
   const dim3 grid(active);
-  if (b->precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_tubes<double>, grid, dim3(rlb::TUBE_BLOCK), 0, b->stream,
-                       reinterpret_cast<double *>(b->pops), b->d_desc, b->d_order, b->d_status);
-  else
-    hipLaunchKernelGGL(rlb::k_tubes<float>, grid, dim3(rlb::TUBE_BLOCK), 0, b->stream,
-                       reinterpret_cast<float *>(b->pops), b->d_desc, b->d_order, b->d_status);
+  with_model(b->order, [&](auto m) {
+    using M = decltype(m);
+    if (b->precision == RLB_FP64)
+      rlb::k_tubes<M, double><<<grid, dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(
+          reinterpret_cast<double *>(b->pops), b->d_desc, b->d_order, b->d_status);
+    else
+      rlb::k_tubes<M, float><<<grid, dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(reinterpret_cast<float *>(b->pops),
+                                                                             b->d_desc, b->d_order, b->d_status);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_tubes launch");
   for (int j = 0; j < b->ntubes; ++j) {
@@ -673,12 +729,16 @@ int rlb_batch_read(rlb_batch *b, int32_t tube, double *n, double *eps, double *U
   }
   const rlb::Geom g = tube_geom(b, tube);
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
-  if (b->precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_read<double>, grid, block, 0, b->stream,
-                       static_cast<const double *>(tube_buf(b, tube, cur)), g, dn, de, dU, dP, b->d_status + tube);
-  else
-    hipLaunchKernelGGL(rlb::k_read<float>, grid, block, 0, b->stream,
-                       static_cast<const float *>(tube_buf(b, tube, cur)), g, dn, de, dU, dP, b->d_status + tube);
+  with_model(b->order, [&](auto m) {
+    using M = decltype(m);
+    if (b->precision == RLB_FP64)
+      rlb::k_read<M, double><<<grid, block, 0, b->stream>>>(static_cast<const double *>(tube_buf(b, tube, cur)), g, dn,
+                                                            de, dU, dP, b->d_status + tube);
+    else
+      rlb::k_read<M, float><<<grid, block, 0, b->stream>>>(static_cast<const float *>(tube_buf(b, tube, cur)), g, dn,
+                                                           de, dU, dP, b->d_status + tube);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_read launch");
   if (!on_device) {
@@ -792,9 +852,16 @@ struct ServeReq {
   int32_t stride = 0;
 };
 
-constexpr int SERVE_TUBE_STREAMS = 2; // one per precision
+// tubes are advanced per group of one precision and one model, each group on
+// its own stream: group = 2 * (precision == mixed) + (order == 2)
+constexpr int SERVE_GROUPS = 4;
+constexpr int SERVE_TUBE_STREAMS = SERVE_GROUPS;
 constexpr int SERVE_BOX_STREAMS = 4;
 constexpr int SERVE_STREAMS = SERVE_TUBE_STREAMS + SERVE_BOX_STREAMS;
+
+int tube_group(int precision, int order) {
+  return 2 * (precision == RLB_MIXED ? 1 : 0) + (order == RLB_ORDER2 ? 1 : 0);
+}
 
 int64_t request_cells(const rlb_request &r) {
   return static_cast<int64_t>(r.nx) * r.ny * r.nz;
@@ -805,6 +872,7 @@ bool request_valid(const rlb_request &r, std::string &why) {
   if (r.kind == RLB_REQ_TUBE && (r.nx != 1 || r.ny != 1)) return why = "a tube needs nx = ny = 1", false;
   if (!valid_dims(r.nx, r.ny, r.nz)) return why = "bad lattice size", false;
   if (r.precision != RLB_FP64 && r.precision != RLB_MIXED) return why = "bad precision", false;
+  if (!valid_order(r.order)) return why = "order must be 0, 2 or 3", false;
   rlb_tube tb{r.nz, r.tau_mode, r.tau, r.eta_s};
   if (!valid_tube(tb)) return why = "bad relaxation", false;
   if (r.steps < 0) return why = "negative steps", false;
@@ -822,11 +890,11 @@ struct rlb_server {
   int max_tubes = 0;
   size_t table_bytes = 0; // front of the pool: tube descriptors, orders, status
   PoolAlloc *alloc = nullptr;
-  rlb::TubeDesc *d_desc[2] = {nullptr, nullptr};
-  int *d_order[2] = {nullptr, nullptr};
+  rlb::TubeDesc *d_desc[SERVE_GROUPS] = {};
+  int *d_order[SERVE_GROUPS] = {};
   unsigned *d_status = nullptr;
-  rlb::TubeDesc *h_desc[2] = {nullptr, nullptr};
-  int *h_order[2] = {nullptr, nullptr};
+  rlb::TubeDesc *h_desc[SERVE_GROUPS] = {};
+  int *h_order[SERVE_GROUPS] = {};
   std::vector<int> free_slots;
   hipStream_t streams[SERVE_STREAMS] = {};
   int next_box_stream = 0;
@@ -849,11 +917,11 @@ struct rlb_server {
 
 namespace {
 
-size_t tube_pair_bytes(const rlb_request &r) { return 2 * tube_buffer_bytes(r.nz, r.precision); }
+size_t tube_pair_bytes(const rlb_request &r) { return 2 * tube_buffer_bytes(r.nz, r.precision, norm_order(r.order)); }
 
 size_t request_bytes_of(const rlb_request &r) {
   if (r.kind == RLB_REQ_TUBE) return tube_pair_bytes(r);
-  return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision));
+  return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision, r.order));
 }
 
 void finish(rlb_server *sv, ServeReq *q, int rc, unsigned flags) {
@@ -890,19 +958,20 @@ int admit(rlb_server *sv, ServeReq *q) {
   q->remaining = r.steps;
   if (r.kind == RLB_REQ_BOX) {
     q->stream_idx = SERVE_TUBE_STREAMS + (sv->next_box_stream++ % SERVE_BOX_STREAMS);
-    rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s};
+    rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s, r.order};
     int rc = rlb_create(&q->box, &cfg, sv->pool + q->off, q->bytes, sv->streams[q->stream_idx]);
     if (rc != RLB_OK) return rc;
     return rlb_init_fields(q->box, f, f + C, f + 2 * C, f + 3 * C, f + 4 * C, 0);
   }
   // tube: two buffers at q->off, staging through the second one
   const size_t eb = elem_bytes(r.precision);
-  const size_t tb = tube_buffer_bytes(r.nz, r.precision);
+  const int order = norm_order(r.order);
+  const size_t tb = tube_buffer_bytes(r.nz, r.precision, order);
   q->stride = static_cast<int32_t>(pop_stride(r.nz, r.precision));
   q->tube_off[0] = static_cast<int64_t>(q->off / eb);
   q->tube_off[1] = static_cast<int64_t>((q->off + tb) / eb);
   q->cur = 0;
-  hipStream_t st = sv->streams[r.precision == RLB_FP64 ? 0 : 1];
+  hipStream_t st = sv->streams[tube_group(r.precision, order)];
   double *stage = reinterpret_cast<double *>(sv->pool + q->off + tb);
   RLB_HIP(hipMemcpyAsync(stage, f, 5 * C * sizeof(double), hipMemcpyHostToDevice, st));
   RLB_HIP(hipMemsetAsync(sv->d_status + q->slot, 0, sizeof(unsigned), st));
@@ -913,12 +982,18 @@ int admit(rlb_server *sv, ServeReq *q) {
   g.cells = r.nz;
   g.stride = q->stride;
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
-  if (r.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_init<double>, grid, block, 0, st, stage, stage + C, stage + 2 * C, stage + 3 * C,
-                       stage + 4 * C, reinterpret_cast<double *>(sv->pool + q->off), g, sv->d_status + q->slot);
-  else
-    hipLaunchKernelGGL(rlb::k_init<float>, grid, block, 0, st, stage, stage + C, stage + 2 * C, stage + 3 * C,
-                       stage + 4 * C, reinterpret_cast<float *>(sv->pool + q->off), g, sv->d_status + q->slot);
+  with_model(order, [&](auto m) {
+    using M = decltype(m);
+    if (r.precision == RLB_FP64)
+      rlb::k_init<M, double><<<grid, block, 0, st>>>(stage, stage + C, stage + 2 * C, stage + 3 * C, stage + 4 * C,
+                                                     reinterpret_cast<double *>(sv->pool + q->off), g,
+                                                     sv->d_status + q->slot);
+    else
+      rlb::k_init<M, float><<<grid, block, 0, st>>>(stage, stage + C, stage + 2 * C, stage + 3 * C, stage + 4 * C,
+                                                    reinterpret_cast<float *>(sv->pool + q->off), g,
+                                                    sv->d_status + q->slot);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "serve k_init");
   RLB_HIP(hipStreamSynchronize(st)); // the staged fields are consumed before the next round reuses the buffer
@@ -935,7 +1010,8 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
   }
   const int64_t C = r.nz;
   const size_t eb = elem_bytes(r.precision);
-  hipStream_t st = sv->streams[r.precision == RLB_FP64 ? 0 : 1];
+  const int order = norm_order(r.order);
+  hipStream_t st = sv->streams[tube_group(r.precision, order)];
   double *stage = reinterpret_cast<double *>(sv->pool + static_cast<size_t>(q->tube_off[1 - q->cur]) * eb);
   char *curp = sv->pool + static_cast<size_t>(q->tube_off[q->cur]) * eb;
   rlb::Geom g;
@@ -946,12 +1022,16 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
   g.stride = q->stride;
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
   double *dn = stage, *de = stage + C, *dU = stage + 2 * C, *dP = stage + 6 * C;
-  if (r.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_read<double>, grid, block, 0, st, reinterpret_cast<const double *>(curp), g, dn, de, dU,
-                       dP, sv->d_status + q->slot);
-  else
-    hipLaunchKernelGGL(rlb::k_read<float>, grid, block, 0, st, reinterpret_cast<const float *>(curp), g, dn, de, dU,
-                       dP, sv->d_status + q->slot);
+  with_model(order, [&](auto m) {
+    using M = decltype(m);
+    if (r.precision == RLB_FP64)
+      rlb::k_read<M, double><<<grid, block, 0, st>>>(reinterpret_cast<const double *>(curp), g, dn, de, dU, dP,
+                                                     sv->d_status + q->slot);
+    else
+      rlb::k_read<M, float><<<grid, block, 0, st>>>(reinterpret_cast<const float *>(curp), g, dn, de, dU, dP,
+                                                    sv->d_status + q->slot);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "serve k_read");
   if (r.out_n) RLB_HIP(hipMemcpyAsync(r.out_n, dn, C * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1000,13 +1080,14 @@ int64_t tube_round_steps(const rlb_server *sv, const ServeReq *q) {
   return std::min<int64_t>(q->remaining, std::max<int64_t>(sv->chunk, budget));
 }
 
-int tubes_advance(rlb_server *sv, int prec) {
-  // all resident tubes of this precision, one persistent launch
+int tubes_advance(rlb_server *sv, int prec, int order) {
+  // all resident tubes of this precision and model, one persistent launch
   std::vector<ServeReq *> tubes;
   for (ServeReq *q : sv->resident)
-    if (q->r.kind == RLB_REQ_TUBE && q->r.precision == prec && q->remaining > 0) tubes.push_back(q);
+    if (q->r.kind == RLB_REQ_TUBE && q->r.precision == prec && norm_order(q->r.order) == order && q->remaining > 0)
+      tubes.push_back(q);
   if (tubes.empty()) return RLB_OK;
-  const int p = prec == RLB_FP64 ? 0 : 1;
+  const int p = tube_group(prec, order);
   std::stable_sort(tubes.begin(), tubes.end(), [&](ServeReq *a, ServeReq *b) {
     return static_cast<double>(a->r.nz) * tube_round_steps(sv, a) >
            static_cast<double>(b->r.nz) * tube_round_steps(sv, b);
@@ -1028,12 +1109,16 @@ int tubes_advance(rlb_server *sv, int prec) {
   hipStream_t st = sv->streams[p];
   RLB_HIP(hipMemcpyAsync(sv->d_desc[p], sv->h_desc[p], sv->max_tubes * sizeof(rlb::TubeDesc), hipMemcpyHostToDevice, st));
   RLB_HIP(hipMemcpyAsync(sv->d_order[p], sv->h_order[p], k * sizeof(int), hipMemcpyHostToDevice, st));
-  if (prec == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_tubes<double>, dim3(k), dim3(rlb::TUBE_BLOCK), 0, st, reinterpret_cast<double *>(sv->pool),
-                       sv->d_desc[p], sv->d_order[p], sv->d_status);
-  else
-    hipLaunchKernelGGL(rlb::k_tubes<float>, dim3(k), dim3(rlb::TUBE_BLOCK), 0, st, reinterpret_cast<float *>(sv->pool),
-                       sv->d_desc[p], sv->d_order[p], sv->d_status);
+  with_model(order, [&](auto m) {
+    using M = decltype(m);
+    if (prec == RLB_FP64)
+      rlb::k_tubes<M, double><<<dim3(k), dim3(rlb::TUBE_BLOCK), 0, st>>>(reinterpret_cast<double *>(sv->pool),
+                                                                          sv->d_desc[p], sv->d_order[p], sv->d_status);
+    else
+      rlb::k_tubes<M, float><<<dim3(k), dim3(rlb::TUBE_BLOCK), 0, st>>>(reinterpret_cast<float *>(sv->pool),
+                                                                         sv->d_desc[p], sv->d_order[p], sv->d_status);
+    return 0;
+  });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "serve k_tubes");
   for (ServeReq *q : tubes) {
@@ -1079,8 +1164,10 @@ void serve_loop(rlb_server *sv) {
     }
     if (sv->resident.empty()) continue;
     // one round
-    int rc = tubes_advance(sv, RLB_FP64);
-    if (rc == RLB_OK) rc = tubes_advance(sv, RLB_MIXED);
+    int rc = RLB_OK;
+    for (int prec : {RLB_FP64, RLB_MIXED})
+      for (int order : {RLB_ORDER3, RLB_ORDER2})
+        if (rc == RLB_OK) rc = tubes_advance(sv, prec, order);
     for (ServeReq *q : sv->resident) {
       if (rc != RLB_OK) break;
       if (q->r.kind != RLB_REQ_BOX || q->remaining == 0) continue;
@@ -1124,7 +1211,7 @@ int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t
   if (chunk_steps < 2 || chunk_steps % 2) return fail(RLB_EINVAL, "rlb_server_create: chunk_steps must be even and >= 2");
   if (max_tubes < 1) return fail(RLB_EINVAL, "rlb_server_create: max_tubes must be >= 1");
   if (reinterpret_cast<uintptr_t>(d_pool) % 256 != 0) return fail(RLB_EINVAL, "rlb_server_create: pool not 256-byte aligned");
-  const size_t table = 2 * align256(max_tubes * sizeof(rlb::TubeDesc)) + 2 * align256(max_tubes * sizeof(int)) +
+  const size_t table = SERVE_GROUPS * (align256(max_tubes * sizeof(rlb::TubeDesc)) + align256(max_tubes * sizeof(int))) +
                        align256(max_tubes * sizeof(unsigned));
   if (pool_bytes <= table) return fail(RLB_ENOMEM, "rlb_server_create: pool too small");
   rlb_server *sv = new (std::nothrow) rlb_server();
@@ -1136,7 +1223,7 @@ int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t
   sv->max_tubes = max_tubes;
   sv->table_bytes = table;
   char *p = sv->pool;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < SERVE_GROUPS; ++k) {
     sv->d_desc[k] = reinterpret_cast<rlb::TubeDesc *>(p);
     p += align256(max_tubes * sizeof(rlb::TubeDesc));
     sv->d_order[k] = reinterpret_cast<int *>(p);
@@ -1145,7 +1232,7 @@ int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t
   sv->d_status = reinterpret_cast<unsigned *>(p);
   // requests are placed after the tables; allocator offsets are from the pool start
   sv->alloc = new PoolAlloc(table, pool_bytes - table);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < SERVE_GROUPS; ++k) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_desc[k]), max_tubes * sizeof(rlb::TubeDesc), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_order[k]), max_tubes * sizeof(int), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -1242,7 +1329,7 @@ void rlb_server_destroy(rlb_server *sv) {
   }
   for (int i = 0; i < SERVE_STREAMS; ++i)
     if (sv->streams[i]) (void)hipStreamDestroy(sv->streams[i]);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < SERVE_GROUPS; ++k) {
     if (sv->h_desc[k]) (void)hipHostFree(sv->h_desc[k]);
     if (sv->h_order[k]) (void)hipHostFree(sv->h_order[k]);
   }

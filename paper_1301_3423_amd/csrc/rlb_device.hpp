@@ -1,12 +1,18 @@
-// Device-side building blocks of one lattice update of the third-order
-// relativistic lattice Boltzmann scheme (Sec. II D, Eq. rlb:disc).
+// Device-side building blocks of one lattice update of the relativistic
+// lattice Boltzmann scheme (Sec. II D, Eq. rlb:disc), generic over the model:
+//   Model<3>: the third-order model, R = sqrt(41), 128 points on 4 energy
+//             shells, equilibrium on the 30 polynomials of Table I
+//             (Eq. equi3rd);
+//   Model<2>: the second-order model of Appendix A, R = 3, 66 points on 3
+//             energy shells, equilibrium on the 14 polynomials of degree
+//             <= 2 (Eq. equi2nd).
 //
 // Every lattice point i is a compile-time constant: its integer displacement
 // theta_i, its shell energy p0_i and its weight w_i come from the quadrature
-// table compiled into the library.  Loops over points are unrolled at compile
-// time, so theta components and weights become instruction immediates and
-// zero components cost nothing.  Points are stored in inversion pairs
-// (2k, 2k+1) with theta_{2k+1} = -theta_{2k}, sorted by shell.
+// tables compiled into the library.  Loops over points are unrolled at
+// compile time, so theta components and weights become instruction
+// immediates and zero components cost nothing.  Points are stored in
+// inversion pairs (2k, 2k+1) with theta_{2k+1} = -theta_{2k}, sorted by shell.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,50 +27,110 @@ struct Point {
   double p0, w;
 };
 
-inline constexpr Point D3Q128[128] = {
+// exponents of p0, px, py, pz in one monomial of an equilibrium basis
+struct Mono {
+  int a0, ax, ay, az;
+};
+
+template <int ORDER>
+struct Model;
+
+// Basis order and blocks follow gen_constants.py, which writes the exact
+// inverse Gram matrices: monomials grouped by the parity of their spatial
+// exponents (G is block diagonal), pz^2 left out (pz^2 = p0^2 - px^2 - py^2
+// on the light cone).
+template <>
+struct Model<3> {
+  static constexpr int ORDER = 3;
+  static constexpr int Q = 128;
+  static constexpr int NSHELL = 4;
+  static constexpr int R2 = 41;
+  static constexpr double R = 0x1.99ccc999fff00p+2;      // sqrt(41)
+  static constexpr double INV_R = 0x1.3fd8077e70577p-3;  // 1/sqrt(41)
+  static constexpr double INV_R2 = 0x1.8f9c18f9c18fap-6; // 1/41
+  static constexpr double INV_R3 = 0x1.f344ba86edcd2p-9; // 1/41^(3/2)
+  // shear viscosity eta = n T (tau - 1/2) / (VISC R)   (Sec. III)
+  static constexpr double VISC = 1.5;
+  static constexpr Point P[Q] = {
 #include "../lattice/d3q128.inc"
+  };
+  static constexpr int NM = 30;
+  static constexpr Mono MONO[NM] = {
+      {0, 0, 0, 0}, {1, 0, 0, 0}, {2, 0, 0, 0}, {3, 0, 0, 0}, {0, 2, 0, 0}, {0, 0, 2, 0}, {1, 2, 0, 0},
+      {1, 0, 2, 0}, {0, 1, 0, 0}, {1, 1, 0, 0}, {2, 1, 0, 0}, {0, 3, 0, 0}, {0, 1, 2, 0}, {0, 0, 1, 0},
+      {1, 0, 1, 0}, {2, 0, 1, 0}, {0, 2, 1, 0}, {0, 0, 3, 0}, {0, 0, 0, 1}, {1, 0, 0, 1}, {2, 0, 0, 1},
+      {0, 2, 0, 1}, {0, 0, 2, 1}, {0, 1, 1, 0}, {1, 1, 1, 0}, {0, 1, 0, 1}, {1, 1, 0, 1}, {0, 0, 1, 1},
+      {1, 0, 1, 1}, {0, 1, 1, 1}};
+  static constexpr int NBLOCK = 8;
+  static constexpr int BLOCK_BEGIN[NBLOCK + 1] = {0, 8, 13, 18, 23, 25, 27, 29, 30};
+  static constexpr double GINV[NM][NM] = {
+#include "rlb_ginv3.inc"
+  };
 };
 
-// Inverse Gram matrix of the 30 light-cone monomials (gen_constants.py).
-inline constexpr double GINV[30][30] = {
-#include "rlb_ginv.inc"
+template <>
+struct Model<2> {
+  static constexpr int ORDER = 2;
+  static constexpr int Q = 66;
+  static constexpr int NSHELL = 3;
+  static constexpr int R2 = 9;
+  static constexpr double R = 3.0;
+  static constexpr double INV_R = 1.0 / 3.0;
+  static constexpr double INV_R2 = 1.0 / 9.0;
+  static constexpr double INV_R3 = 1.0 / 27.0;
+  // eta_2nd = n T (tau - 1/2) / (7 R), the fit of Appendix A
+  static constexpr double VISC = 7.0;
+  static constexpr Point P[Q] = {
+#include "../lattice/d3q66.inc"
+  };
+  static constexpr int NM = 14;
+  static constexpr Mono MONO[NM] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {2, 0, 0, 0}, {0, 2, 0, 0}, {0, 0, 2, 0},
+                                    {0, 1, 0, 0}, {1, 1, 0, 0}, {0, 0, 1, 0}, {1, 0, 1, 0}, {0, 0, 0, 1},
+                                    {1, 0, 0, 1}, {0, 1, 1, 0}, {0, 1, 0, 1}, {0, 0, 1, 1}};
+  static constexpr int NBLOCK = 7;
+  static constexpr int BLOCK_BEGIN[NBLOCK + 1] = {0, 5, 7, 9, 11, 12, 13, 14};
+  static constexpr double GINV[NM][NM] = {
+#include "rlb_ginv2.inc"
+  };
 };
 
-inline constexpr int Q = 128;
-inline constexpr int NPAIR = Q / 2;
-inline constexpr int NSHELL = 4;
-inline constexpr int R2 = 41;
-inline constexpr double R = 0x1.99ccc999fff00p+2;      // sqrt(41)
-inline constexpr double INV_R = 0x1.3fd8077e70577p-3;  // 1/sqrt(41)
-inline constexpr double INV_R2 = 0x1.8f9c18f9c18fap-6; // 1/41
-inline constexpr double INV_R3 = 0x1.f344ba86edcd2p-9; // 1/41^(3/2)
-inline constexpr int MAXD = 6;                         // max |theta component|
+using M3 = Model<3>;
+using M2 = Model<2>;
+
+inline constexpr int MAXD = 6; // largest |theta component| of either table
 
 inline constexpr unsigned FLAG_NONFINITE = 1u;
 inline constexpr unsigned FLAG_NONPHYSICAL = 2u;
 inline constexpr unsigned FLAG_LANDAU = 4u;
 
-// ---- compile-time facts about the table --------------------------------
+// ---- compile-time facts about a table ------------------------------------
 
+template <class M>
 constexpr bool table_is_paired() {
-  for (int k = 0; k < NPAIR; ++k) {
-    const Point &a = D3Q128[2 * k], &b = D3Q128[2 * k + 1];
+  for (int k = 0; k < M::Q / 2; ++k) {
+    const Point &a = M::P[2 * k], &b = M::P[2 * k + 1];
     if (a.tx != -b.tx || a.ty != -b.ty || a.tz != -b.tz) return false;
     if (a.shell != b.shell || a.p0 != b.p0 || a.w != b.w) return false;
-    if (a.tx * a.tx + a.ty * a.ty + a.tz * a.tz != R2) return false;
+    if (a.tx * a.tx + a.ty * a.ty + a.tz * a.tz != M::R2) return false;
+    if (a.tx > MAXD || -a.tx > MAXD || a.ty > MAXD || -a.ty > MAXD || a.tz > MAXD || -a.tz > MAXD) return false;
   }
-  for (int i = 1; i < Q; ++i)
-    if (D3Q128[i].shell < D3Q128[i - 1].shell) return false;
-  return true;
+  for (int i = 1; i < M::Q; ++i)
+    if (M::P[i].shell < M::P[i - 1].shell) return false;
+  return M::P[M::Q - 1].shell == M::NSHELL - 1;
 }
-static_assert(table_is_paired(), "quadrature table must be inversion-paired and shell-sorted");
+static_assert(table_is_paired<M3>(), "third-order table must be inversion-paired and shell-sorted");
+static_assert(table_is_paired<M2>(), "second-order table must be inversion-paired and shell-sorted");
 
+template <class M>
 constexpr int shell_pair_begin(int l) {
-  for (int k = 0; k < NPAIR; ++k)
-    if (D3Q128[2 * k].shell >= l) return k;
-  return NPAIR;
+  for (int k = 0; k < M::Q / 2; ++k)
+    if (M::P[2 * k].shell >= l) return k;
+  return M::Q / 2;
 }
-constexpr double shell_p0(int l) { return D3Q128[2 * shell_pair_begin(l)].p0; }
+template <class M>
+constexpr double shell_p0(int l) {
+  return M::P[2 * shell_pair_begin<M>(l)].p0;
+}
 
 // Fused multiply-add in the precision of its operands (the double builtin
 // would silently promote float arithmetic).
@@ -131,42 +197,39 @@ struct Moments {
   double T00, T0x, T0y, T0z, Txx, Tyy, Tzz, Txy, Txz, Tyz;
 };
 
-// N^mu = sum_i f_i p_i^mu and T^{mu nu} = sum_i f_i p_i^mu p_i^nu, using
-// the pairs: with s = f_i + f_inv(i) and d = f_i - f_inv(i), the even
-// moments take s and the odd ones d.  Sums per shell carry integer theta
-// factors; the energy and R powers are applied once per shell.  Always
-// accumulated in float64.
-template <class S>
-__device__ __forceinline__ Moments moments(const S (&f)[Q]) {
-  Moments m{};
-  static_for<0, NSHELL>([&](auto L) {
-    constexpr int l = decltype(L)::value;
-    constexpr int kb = shell_pair_begin(l), ke = shell_pair_begin(l + 1);
-    double sh = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0, dx = 0, dy = 0, dz = 0;
-    static_for<kb, ke>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
-      const double a = static_cast<double>(f[2 * k]);
-      const double b = static_cast<double>(f[2 * k + 1]);
-      const double s = a + b, d = a - b;
-      sh += s;
-      if constexpr (P.tx != 0) sxx = __builtin_fma(double(P.tx * P.tx), s, sxx);
-      if constexpr (P.ty != 0) syy = __builtin_fma(double(P.ty * P.ty), s, syy);
-      if constexpr (P.tz != 0) szz = __builtin_fma(double(P.tz * P.tz), s, szz);
-      if constexpr (P.tx * P.ty != 0) sxy = __builtin_fma(double(P.tx * P.ty), s, sxy);
-      if constexpr (P.tx * P.tz != 0) sxz = __builtin_fma(double(P.tx * P.tz), s, sxz);
-      if constexpr (P.ty * P.tz != 0) syz = __builtin_fma(double(P.ty * P.tz), s, syz);
-      if constexpr (P.tx != 0) dx = __builtin_fma(double(P.tx), d, dx);
-      if constexpr (P.ty != 0) dy = __builtin_fma(double(P.ty), d, dy);
-      if constexpr (P.tz != 0) dz = __builtin_fma(double(P.tz), d, dz);
-      // finish this pair before the next: otherwise the even chains are sunk
-      // to the end of the shell and every s stays live (an empty statement
-      // that reads and writes the accumulators; it emits no instruction)
-      asm volatile("" : "+v"(sh), "+v"(sxx), "+v"(syy), "+v"(szz), "+v"(sxy), "+v"(sxz), "+v"(syz), "+v"(dx),
-                   "+v"(dy), "+v"(dz));
-    });
-    constexpr double p = shell_p0(l);
-    constexpr double p1r = p * INV_R, p2 = p * p, p2r = p * p * INV_R, p2r2 = p * p * INV_R2;
+// Integer-weighted sums over the pairs of one shell: sh = sum s,
+// sab = sum theta_a theta_b s, da = sum theta_a d, with s = f_i + f_inv(i)
+// and d = f_i - f_inv(i).
+struct ShellSums {
+  double sh, sxx, syy, szz, sxy, sxz, syz, dx, dy, dz;
+
+  template <class M, int K>
+  __device__ __forceinline__ void add_pair(double s, double d) {
+    constexpr Point P = M::P[2 * K];
+    sh += s;
+    if constexpr (P.tx != 0) sxx = __builtin_fma(double(P.tx * P.tx), s, sxx);
+    if constexpr (P.ty != 0) syy = __builtin_fma(double(P.ty * P.ty), s, syy);
+    if constexpr (P.tz != 0) szz = __builtin_fma(double(P.tz * P.tz), s, szz);
+    if constexpr (P.tx * P.ty != 0) sxy = __builtin_fma(double(P.tx * P.ty), s, sxy);
+    if constexpr (P.tx * P.tz != 0) sxz = __builtin_fma(double(P.tx * P.tz), s, sxz);
+    if constexpr (P.ty * P.tz != 0) syz = __builtin_fma(double(P.ty * P.tz), s, syz);
+    if constexpr (P.tx != 0) dx = __builtin_fma(double(P.tx), d, dx);
+    if constexpr (P.ty != 0) dy = __builtin_fma(double(P.ty), d, dy);
+    if constexpr (P.tz != 0) dz = __builtin_fma(double(P.tz), d, dz);
+  }
+  // Finish this pair before the next: otherwise the compiler sinks the even
+  // chains to the end of the shell and every s stays live.  An empty
+  // statement that reads and writes the accumulators; it emits nothing.
+  __device__ __forceinline__ void pin() {
+    asm volatile("" : "+v"(sh), "+v"(sxx), "+v"(syy), "+v"(szz), "+v"(sxy), "+v"(sxz), "+v"(syz), "+v"(dx),
+                 "+v"(dy), "+v"(dz));
+  }
+  // Folds the sums of shell L into the moments: the energy and R powers of
+  // the shell are applied once.
+  template <class M, int L>
+  __device__ __forceinline__ void fold(Moments &m) const {
+    constexpr double p = shell_p0<M>(L);
+    constexpr double p1r = p * M::INV_R, p2 = p * p, p2r = p * p * M::INV_R, p2r2 = p * p * M::INV_R2;
     m.N0 = __builtin_fma(p, sh, m.N0);
     m.T00 = __builtin_fma(p2, sh, m.T00);
     m.Nx = __builtin_fma(p1r, dx, m.Nx);
@@ -181,6 +244,26 @@ __device__ __forceinline__ Moments moments(const S (&f)[Q]) {
     m.Txy = __builtin_fma(p2r2, sxy, m.Txy);
     m.Txz = __builtin_fma(p2r2, sxz, m.Txz);
     m.Tyz = __builtin_fma(p2r2, syz, m.Tyz);
+  }
+};
+
+// N^mu = sum_i f_i p_i^mu and T^{mu nu} = sum_i f_i p_i^mu p_i^nu with
+// p_i = p0_i (1, theta_i / R), from the pair sums of each shell.  Always
+// accumulated in float64.
+template <class M, class S>
+__device__ __forceinline__ Moments moments(const S (&f)[M::Q]) {
+  Moments m{};
+  static_for<0, M::NSHELL>([&](auto L) {
+    constexpr int l = decltype(L)::value;
+    ShellSums a{};
+    static_for<shell_pair_begin<M>(l), shell_pair_begin<M>(l + 1)>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      const double x = static_cast<double>(f[2 * k]);
+      const double y = static_cast<double>(f[2 * k + 1]);
+      a.template add_pair<M, k>(x + y, x - y);
+      a.pin();
+    });
+    a.template fold<M, l>(m);
   });
   return m;
 }
@@ -264,80 +347,94 @@ struct Relax {
   double eta_s; // ratio eta/s
 };
 
+// From eta = n T (tau - 1/2) / (VISC R) and the entropy density
+// s = 4 n - n ln(n / T^3):  tau = 1/2 + (VISC R / T) (eta/s) (4 - ln(n/T^3)).
+template <class M>
 __device__ __forceinline__ double relaxation_time(const Relax &r, double n, double T) {
   if (r.mode == 0) return r.tau;
-  return 0.5 + (1.5 * R / T) * r.eta_s * (4.0 - log(n / (T * T * T)));
+  return 0.5 + (M::VISC * M::R / T) * r.eta_s * (4.0 - log(n / (T * T * T)));
 }
 
 // ---- equilibrium (step 5) ---------------------------------------------------
 
 // Coefficients c of the projected Maxwell-Juttner distribution in the
 // monomial basis: c = G^-1 M, with M the moments of the continuous
-// distribution (Z = n/(2T), N = nU, T = nT(4UU - eta),
-// P = 4nT^2(6UUU - eta U - eta U - eta U)) of each monomial.  G^-1 is block
-// diagonal by the parity class of the monomials, so M is formed one block
-// at a time (at most eight values live).
+// distribution of each basis monomial.  G^-1 is block diagonal by the
+// parity class of the monomials, so M is formed one block at a time (at
+// most eight values live).
+template <class M>
 struct EqCoef {
-  double c[30];
+  double c[M::NM];
 };
 
-inline constexpr int CLASS_BEGIN[9] = {0, 8, 13, 18, 23, 25, 27, 29, 30};
-
+// Moments of the Maxwell-Juttner distribution for the equation of state
+// eps = 3 n T:  Z = n/(2T) for the constant monomial, N^mu = n U^mu,
+// T^{mu nu} = n T (4 U^mu U^nu - eta^{mu nu}) and
+// P^{mu nu lambda} = 4 n T^2 (6 U U U - eta U - eta U - eta U) (symmetrised),
+// with eta = diag(1, -1, -1, -1).
 struct MJ {
-  double n, a, b, U0, Ux, Uy, Uz, Z; // a = nT, b = 4 n T^2, Z = n/(2T)
-  template <int IDX>
+  double n, a, b, Z; // a = nT, b = 4 n T^2, Z = n/(2T)
+  double u[4];       // U^mu
+
+  static constexpr double eta(int i, int j) { return i != j ? 0.0 : (i == 0 ? 1.0 : -1.0); }
+
+  // the moment of the monomial p0^A0 px^AX py^AY pz^AZ
+  template <int A0, int AX, int AY, int AZ>
   __device__ __forceinline__ double moment() const {
-    if constexpr (IDX == 0) return Z;
-    else if constexpr (IDX == 1) return n * U0;
-    else if constexpr (IDX == 2) return a * (4.0 * U0 * U0 - 1.0);
-    else if constexpr (IDX == 3) return b * U0 * (6.0 * U0 * U0 - 3.0);
-    else if constexpr (IDX == 4) return a * (4.0 * Ux * Ux + 1.0);
-    else if constexpr (IDX == 5) return a * (4.0 * Uy * Uy + 1.0);
-    else if constexpr (IDX == 6) return b * U0 * (6.0 * Ux * Ux + 1.0);
-    else if constexpr (IDX == 7) return b * U0 * (6.0 * Uy * Uy + 1.0);
-    else if constexpr (IDX == 8) return n * Ux;
-    else if constexpr (IDX == 9) return 4.0 * a * U0 * Ux;
-    else if constexpr (IDX == 10) return b * Ux * (6.0 * U0 * U0 - 1.0);
-    else if constexpr (IDX == 11) return b * Ux * (6.0 * Ux * Ux + 3.0);
-    else if constexpr (IDX == 12) return b * Ux * (6.0 * Uy * Uy + 1.0);
-    else if constexpr (IDX == 13) return n * Uy;
-    else if constexpr (IDX == 14) return 4.0 * a * U0 * Uy;
-    else if constexpr (IDX == 15) return b * Uy * (6.0 * U0 * U0 - 1.0);
-    else if constexpr (IDX == 16) return b * Uy * (6.0 * Ux * Ux + 1.0);
-    else if constexpr (IDX == 17) return b * Uy * (6.0 * Uy * Uy + 3.0);
-    else if constexpr (IDX == 18) return n * Uz;
-    else if constexpr (IDX == 19) return 4.0 * a * U0 * Uz;
-    else if constexpr (IDX == 20) return b * Uz * (6.0 * U0 * U0 - 1.0);
-    else if constexpr (IDX == 21) return b * Uz * (6.0 * Ux * Ux + 1.0);
-    else if constexpr (IDX == 22) return b * Uz * (6.0 * Uy * Uy + 1.0);
-    else if constexpr (IDX == 23) return 4.0 * a * Ux * Uy;
-    else if constexpr (IDX == 24) return 6.0 * b * U0 * Ux * Uy;
-    else if constexpr (IDX == 25) return 4.0 * a * Ux * Uz;
-    else if constexpr (IDX == 26) return 6.0 * b * U0 * Ux * Uz;
-    else if constexpr (IDX == 27) return 4.0 * a * Uy * Uz;
-    else if constexpr (IDX == 28) return 6.0 * b * U0 * Uy * Uz;
-    else return 6.0 * b * Ux * Uy * Uz;
+    constexpr int D = A0 + AX + AY + AZ;
+    // the tensor indices of the monomial in ascending order
+    constexpr int i = A0 > 0 ? 0 : (A0 + AX > 0 ? 1 : (A0 + AX + AY > 0 ? 2 : 3));
+    constexpr int j = A0 > 1 ? 0 : (A0 + AX > 1 ? 1 : (A0 + AX + AY > 1 ? 2 : 3));
+    constexpr int k = A0 > 2 ? 0 : (A0 + AX > 2 ? 1 : (A0 + AX + AY > 2 ? 2 : 3));
+    if constexpr (D == 0) {
+      return Z;
+    } else if constexpr (D == 1) {
+      return n * u[i];
+    } else if constexpr (D == 2) {
+      if constexpr (eta(i, j) != 0.0)
+        return a * (4.0 * u[i] * u[j] - eta(i, j));
+      else
+        return 4.0 * a * u[i] * u[j];
+    } else {
+      static_assert(D == 3, "equilibrium monomials have degree <= 3");
+      constexpr double e = eta(i, j) + eta(i, k) + eta(j, k);
+      // at most one pair of equal indices unless all three are equal
+      if constexpr (i == j && j == k)
+        return b * u[i] * (6.0 * u[i] * u[i] - 3.0 * eta(i, i));
+      else if constexpr (eta(i, j) != 0.0)
+        return b * u[k] * (6.0 * u[i] * u[j] - eta(i, j));
+      else if constexpr (eta(j, k) != 0.0)
+        return b * u[i] * (6.0 * u[j] * u[k] - eta(j, k));
+      else if constexpr (eta(i, k) != 0.0)
+        return b * u[j] * (6.0 * u[i] * u[k] - eta(i, k));
+      else {
+        static_assert(e == 0.0);
+        return 6.0 * b * u[i] * u[j] * u[k];
+      }
+    }
   }
 };
 
-__device__ __forceinline__ EqCoef eq_coefficients(double n, double T, double U0, double Ux, double Uy,
-                                                  double Uz) {
-  const MJ mj{n, n * T, 4.0 * n * T * T, U0, Ux, Uy, Uz, n / (2.0 * T)};
-  EqCoef e;
-  static_for<0, 8>([&](auto B) {
+template <class M>
+__device__ __forceinline__ EqCoef<M> eq_coefficients(double n, double T, double U0, double Ux, double Uy,
+                                                     double Uz) {
+  const MJ mj{n, n * T, 4.0 * n * T * T, n / (2.0 * T), {U0, Ux, Uy, Uz}};
+  EqCoef<M> e;
+  static_for<0, M::NBLOCK>([&](auto B) {
     constexpr int blk = decltype(B)::value;
-    constexpr int b0 = CLASS_BEGIN[blk], b1 = CLASS_BEGIN[blk + 1];
-    double M[b1 - b0];
+    constexpr int b0 = M::BLOCK_BEGIN[blk], b1 = M::BLOCK_BEGIN[blk + 1];
+    double Mb[b1 - b0];
     static_for<b0, b1>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      M[j - b0] = mj.template moment<j>();
+      constexpr Mono mo = M::MONO[j];
+      Mb[j - b0] = mj.template moment<mo.a0, mo.ax, mo.ay, mo.az>();
     });
     static_for<b0, b1>([&](auto A) {
       constexpr int ia = decltype(A)::value;
       double acc = 0.0;
       static_for<b0, b1>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        if constexpr (GINV[ia][j] != 0.0) acc = __builtin_fma(GINV[ia][j], M[j - b0], acc);
+        if constexpr (M::GINV[ia][j] != 0.0) acc = __builtin_fma(M::GINV[ia][j], Mb[j - b0], acc);
       });
       e.c[ia] = acc;
     });
@@ -345,64 +442,108 @@ __device__ __forceinline__ EqCoef eq_coefficients(double n, double T, double U0,
   return e;
 }
 
-// The equilibrium on one energy shell p = p0_l as a cubic polynomial of the
-// integer direction theta:  h = E(theta) + O(theta), even and odd parts,
-//   E = A + Bxx tx^2 + Byy ty^2 + Bxy tx ty + Bxz tx tz + Byz ty tz
-//   O = Cx tx + Cy ty + Cz tz + D111 tx^3 + D122 tx ty^2 + D112 tx^2 ty
-//       + D222 ty^3 + D113 tx^2 tz + D223 ty^2 tz + D123 tx ty tz,
-// so that f_i^eq = w_i (E + O) and f_inv(i)^eq = w_i (E - O).
-template <class CT>
-struct ShellCoef {
-  CT A, Bxx, Byy, Bxy, Bxz, Byz;
-  CT Cx, Cy, Cz, D111, D122, D112, D222, D113, D223, D123;
+// On shell l (p0 = p), the basis monomial (a0, ax, ay, az) equals
+// p^(a0+ax+ay+az) R^-(ax+ay+az) tx^ax ty^ay tz^az, so the equilibrium there
+// is a polynomial in the integer direction theta whose coefficient of
+// tx^ax ty^ay tz^az collects the basis coefficients with that spatial part.
+// SPATIAL<M> lists the distinct spatial parts of the basis in order of
+// first appearance (16 for the third-order basis, 9 for the second-order).
+constexpr bool same_spatial(const Mono &a, const Mono &b) { return a.ax == b.ax && a.ay == b.ay && a.az == b.az; }
+
+template <class M>
+constexpr int spatial_count() {
+  int n = 0;
+  for (int j = 0; j < M::NM; ++j) {
+    bool seen = false;
+    for (int i = 0; i < j; ++i) seen = seen || same_spatial(M::MONO[i], M::MONO[j]);
+    n += seen ? 0 : 1;
+  }
+  return n;
+}
+
+template <class M>
+struct SpatialTable {
+  static constexpr int NS = spatial_count<M>();
+  Mono part[NS]; // a0 unused
+  int of[M::NM]; // spatial index of each basis monomial
 };
 
-template <int L, class CT>
-__device__ __forceinline__ ShellCoef<CT> shell_coefficients(const EqCoef &e) {
-  constexpr double p = shell_p0(L);
-  constexpr double q2 = p * p * INV_R2, q3 = p * p * p * INV_R2, r1 = p * INV_R, r2 = p * p * INV_R,
-                   r3 = p * p * p * INV_R, d3 = p * p * p * INV_R3;
-  const double *c = e.c;
-  ShellCoef<CT> s;
-  s.A = CT(__builtin_fma(p, __builtin_fma(p, __builtin_fma(p, c[3], c[2]), c[1]), c[0]));
-  s.Bxx = CT(__builtin_fma(q3, c[6], q2 * c[4]));
-  s.Byy = CT(__builtin_fma(q3, c[7], q2 * c[5]));
-  s.Bxy = CT(__builtin_fma(q3, c[24], q2 * c[23]));
-  s.Bxz = CT(__builtin_fma(q3, c[26], q2 * c[25]));
-  s.Byz = CT(__builtin_fma(q3, c[28], q2 * c[27]));
-  s.Cx = CT(__builtin_fma(r3, c[10], __builtin_fma(r2, c[9], r1 * c[8])));
-  s.Cy = CT(__builtin_fma(r3, c[15], __builtin_fma(r2, c[14], r1 * c[13])));
-  s.Cz = CT(__builtin_fma(r3, c[20], __builtin_fma(r2, c[19], r1 * c[18])));
-  s.D111 = CT(d3 * c[11]);
-  s.D122 = CT(d3 * c[12]);
-  s.D112 = CT(d3 * c[16]);
-  s.D222 = CT(d3 * c[17]);
-  s.D113 = CT(d3 * c[21]);
-  s.D223 = CT(d3 * c[22]);
-  s.D123 = CT(d3 * c[29]);
+template <class M>
+constexpr SpatialTable<M> make_spatial() {
+  SpatialTable<M> t{};
+  int n = 0;
+  for (int j = 0; j < M::NM; ++j) {
+    int found = -1;
+    for (int s = 0; s < n; ++s)
+      if (same_spatial(t.part[s], M::MONO[j])) found = s;
+    if (found < 0) {
+      t.part[n] = Mono{0, M::MONO[j].ax, M::MONO[j].ay, M::MONO[j].az};
+      found = n++;
+    }
+    t.of[j] = found;
+  }
+  return t;
+}
+
+template <class M>
+inline constexpr SpatialTable<M> SPATIAL = make_spatial<M>();
+
+template <class M, class CT>
+struct ShellCoef {
+  CT c[SpatialTable<M>::NS];
+};
+
+constexpr double ipow(double x, int e) { return e == 0 ? 1.0 : x * ipow(x, e - 1); }
+constexpr int ipow(int x, int e) { return e == 0 ? 1 : x * ipow(x, e - 1); }
+
+template <class M>
+constexpr double inv_r_pow(int e) {
+  return e == 0 ? 1.0 : e == 1 ? M::INV_R : e == 2 ? M::INV_R2 : M::INV_R3;
+}
+
+// Coefficients of the theta-polynomial of shell L, rounded once to CT.
+// The terms of one spatial part are accumulated from the highest energy
+// power down.
+template <class M, int L, class CT>
+__device__ __forceinline__ ShellCoef<M, CT> shell_coefficients(const EqCoef<M> &e) {
+  constexpr double p = shell_p0<M>(L);
+  ShellCoef<M, CT> s;
+  static_for<0, SpatialTable<M>::NS>([&](auto Sx) {
+    constexpr int si = decltype(Sx)::value;
+    double acc = 0.0;
+    static_for<0, M::NM>([&](auto J) {
+      constexpr int j = M::NM - 1 - decltype(J)::value;
+      if constexpr (SPATIAL<M>.of[j] == si) {
+        constexpr Mono mo = M::MONO[j];
+        constexpr int sd = mo.ax + mo.ay + mo.az;
+        constexpr double k = ipow(p, mo.a0 + sd) * inv_r_pow<M>(sd);
+        acc = __builtin_fma(k, e.c[j], acc);
+      }
+    });
+    s.c[si] = CT(acc);
+  });
   return s;
 }
 
-template <int IDX, class CT>
-__device__ __forceinline__ void shell_eval(const ShellCoef<CT> &s, CT &Ev, CT &Od) {
-  constexpr int tx = D3Q128[IDX].tx, ty = D3Q128[IDX].ty, tz = D3Q128[IDX].tz;
-  CT E = s.A;
-  if constexpr (tx != 0) E = fmadd(CT(tx * tx), s.Bxx, E);
-  if constexpr (ty != 0) E = fmadd(CT(ty * ty), s.Byy, E);
-  if constexpr (tx * ty != 0) E = fmadd(CT(tx * ty), s.Bxy, E);
-  if constexpr (tx * tz != 0) E = fmadd(CT(tx * tz), s.Bxz, E);
-  if constexpr (ty * tz != 0) E = fmadd(CT(ty * tz), s.Byz, E);
+// Even (E) and odd (O) parts of the theta-polynomial at point IDX, so that
+// f_IDX^eq = w (E + O) and f_inv(IDX)^eq = w (E - O).
+template <class M, int IDX, class CT>
+__device__ __forceinline__ void shell_eval(const ShellCoef<M, CT> &s, CT &Ev, CT &Od) {
+  constexpr Point P = M::P[IDX];
+  CT E = s.c[0]; // spatial part 0 is the constant
+  static_assert(SPATIAL<M>.part[0].ax + SPATIAL<M>.part[0].ay + SPATIAL<M>.part[0].az == 0);
   CT O = CT(0);
-  if constexpr (tx != 0) O = fmadd(CT(tx), s.Cx, O);
-  if constexpr (ty != 0) O = fmadd(CT(ty), s.Cy, O);
-  if constexpr (tz != 0) O = fmadd(CT(tz), s.Cz, O);
-  if constexpr (tx != 0) O = fmadd(CT(tx * tx * tx), s.D111, O);
-  if constexpr (tx * ty != 0) O = fmadd(CT(tx * ty * ty), s.D122, O);
-  if constexpr (tx * ty != 0) O = fmadd(CT(tx * tx * ty), s.D112, O);
-  if constexpr (ty != 0) O = fmadd(CT(ty * ty * ty), s.D222, O);
-  if constexpr (tx * tz != 0) O = fmadd(CT(tx * tx * tz), s.D113, O);
-  if constexpr (ty * tz != 0) O = fmadd(CT(ty * ty * tz), s.D223, O);
-  if constexpr (tx * ty * tz != 0) O = fmadd(CT(tx * ty * tz), s.D123, O);
+  static_for<1, SpatialTable<M>::NS>([&](auto Sx) {
+    constexpr int si = decltype(Sx)::value;
+    constexpr Mono sp = SPATIAL<M>.part[si];
+    constexpr int mono = ipow(P.tx, sp.ax) * ipow(P.ty, sp.ay) * ipow(P.tz, sp.az);
+    if constexpr (mono != 0) {
+      if constexpr ((sp.ax + sp.ay + sp.az) % 2 == 0)
+        E = fmadd(CT(mono), s.c[si], E);
+      else
+        O = fmadd(CT(mono), s.c[si], O);
+    }
+  });
   Ev = E;
   Od = O;
 }

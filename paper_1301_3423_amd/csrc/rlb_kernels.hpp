@@ -38,13 +38,13 @@ __device__ __forceinline__ void cell_coords(int cell, const Geom &g, int &x, int
   z = yz / g.ny;
 }
 
-// Gather f_i(x, t) for all 128 points (pull streaming).
-template <class S>
+// Gather f_i(x, t) for all points of the model (pull streaming).
+template <class M, class S>
 __device__ __forceinline__ void gather(const S *__restrict__ cur, const Geom &g, const Shifts &sh,
-                                       S (&f)[Q]) {
-  static_for<0, Q>([&](auto I) {
+                                       S (&f)[M::Q]) {
+  static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    constexpr Point P = D3Q128[i];
+    constexpr Point P = M::P[i];
     f[i] = load_at(cur + i * g.stride, sh.back<P.tx, P.ty, P.tz>());
   });
 }
@@ -53,21 +53,21 @@ __device__ __forceinline__ void gather(const S *__restrict__ cur, const Geom &g,
 // right side) of all points of one cell, written through `put(i, value)`.
 // The rate p_i^mu U_mu / (tau p_i^0) = (gamma/tau)(1 - theta_i.v/R)
 // = g - t_i for point i and g + t_i for its inverse.
-template <class S, class Put>
-__device__ __forceinline__ void relax_cell(const S (&f)[Q], const Frame &fr, double tau, Put &&put) {
+template <class M, class S, class Put>
+__device__ __forceinline__ void relax_cell(const S (&f)[M::Q], const Frame &fr, double tau, Put &&put) {
   using CT = S; // per-population arithmetic in the storage precision
-  const EqCoef e = eq_coefficients(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
+  const EqCoef<M> e = eq_coefficients<M>(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
   const double g = fr.U0 / tau;
   const CT gg = CT(g);
-  const CT bx = CT(g * fr.vx * INV_R), by = CT(g * fr.vy * INV_R), bz = CT(g * fr.vz * INV_R);
-  static_for<0, NSHELL>([&](auto L) {
+  const CT bx = CT(g * fr.vx * M::INV_R), by = CT(g * fr.vy * M::INV_R), bz = CT(g * fr.vz * M::INV_R);
+  static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const ShellCoef<CT> s = shell_coefficients<l, CT>(e);
-    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+    const ShellCoef<M, CT> s = shell_coefficients<M, l, CT>(e);
+    static_for<shell_pair_begin<M>(l), shell_pair_begin<M>(l + 1)>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
+      constexpr Point P = M::P[2 * k];
       CT E, O;
-      shell_eval<2 * k, CT>(s, E, O);
+      shell_eval<M, 2 * k, CT>(s, E, O);
       const CT wE = CT(P.w) * E, wO = CT(P.w) * O;
       CT t = CT(0);
       if constexpr (P.tx != 0) t = fmadd(CT(P.tx), bx, t);
@@ -145,19 +145,28 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Float64 populations of the last STASH_N pairs wait in LDS between the
-// moment sums and the relaxation (64 KB per 256-thread block), which keeps
-// the live registers of the float64 kernels within two waves per SIMD.
-inline constexpr int STASH_N = 32;
-inline constexpr int STASH_BEGIN = NPAIR - STASH_N;
+// Float64 populations of the last stash_n pairs of the third-order model
+// wait in LDS between the moment sums and the relaxation (64 KB per
+// 256-thread block), which keeps the live registers of the float64 kernels
+// within two waves per SIMD.  The 33 pairs of the second-order model fit
+// in registers.
+template <class M, class S>
+inline constexpr int stash_n = (sizeof(S) == 8 && M::Q == 128) ? 32 : 0;
+template <class M, class S>
+inline constexpr int stash_begin = M::Q / 2 - stash_n<M, S>;
+// LDS rows to declare (at least one)
+template <class M, class S>
+inline constexpr int stash_rows = stash_n<M, S> > 0 ? stash_n<M, S> : 1;
 
 // One lattice update of `cell` by the two lanes (c, c + 32) of a wavefront
 // (see above); `lds` is the block's stash of the last shell (float64 only,
-// [STASH_N][block size]).  Cells at or beyond g.cells are computed for a
+// [stash_n][block size]).  Cells at or beyond g.cells are computed for a
 // clamped cell and never stored.  OR-s this cell's flags into `flags`.
-template <class S, int TB>
+template <class M, class S, int TB>
 __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__restrict__ nxt, const Geom &g,
                                                const Relax &rx, int cell, S (*lds)[TB], unsigned &flags) {
+  constexpr int NPAIR = M::Q / 2;
+  constexpr int STASH_BEGIN = stash_begin<M, S>;
   const int lane = threadIdx.x & 63;
   const int m = lane >> 5;
   const int sigma = 1 - 2 * m;
@@ -170,48 +179,23 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
     const HalfShifts sh(x, y, z, sigma, m, g);
     static_for<0, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
+      constexpr Point P = M::P[2 * k];
       f[k] = load_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>());
     });
   }
   // moments of this lane's members; odd sums carry theta of point 2k
   Moments mo{};
-  static_for<0, NSHELL>([&](auto L) {
+  static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
-    double sh = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0, dx = 0, dy = 0, dz = 0;
-    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+    ShellSums a{};
+    static_for<shell_pair_begin<M>(l), shell_pair_begin<M>(l + 1)>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
       const double v = static_cast<double>(f[k]);
-      sh += v;
-      if constexpr (P.tx != 0) sxx = __builtin_fma(double(P.tx * P.tx), v, sxx);
-      if constexpr (P.ty != 0) syy = __builtin_fma(double(P.ty * P.ty), v, syy);
-      if constexpr (P.tz != 0) szz = __builtin_fma(double(P.tz * P.tz), v, szz);
-      if constexpr (P.tx * P.ty != 0) sxy = __builtin_fma(double(P.tx * P.ty), v, sxy);
-      if constexpr (P.tx * P.tz != 0) sxz = __builtin_fma(double(P.tx * P.tz), v, sxz);
-      if constexpr (P.ty * P.tz != 0) syz = __builtin_fma(double(P.ty * P.tz), v, syz);
-      if constexpr (P.tx != 0) dx = __builtin_fma(double(P.tx), v, dx);
-      if constexpr (P.ty != 0) dy = __builtin_fma(double(P.ty), v, dy);
-      if constexpr (P.tz != 0) dz = __builtin_fma(double(P.tz), v, dz);
+      a.template add_pair<M, k>(v, v);
     });
-    constexpr double p = shell_p0(l);
-    constexpr double p1r = p * INV_R, p2 = p * p, p2r = p * p * INV_R, p2r2 = p * p * INV_R2;
-    mo.N0 = __builtin_fma(p, sh, mo.N0);
-    mo.T00 = __builtin_fma(p2, sh, mo.T00);
-    mo.Nx = __builtin_fma(p1r, dx, mo.Nx);
-    mo.Ny = __builtin_fma(p1r, dy, mo.Ny);
-    mo.Nz = __builtin_fma(p1r, dz, mo.Nz);
-    mo.T0x = __builtin_fma(p2r, dx, mo.T0x);
-    mo.T0y = __builtin_fma(p2r, dy, mo.T0y);
-    mo.T0z = __builtin_fma(p2r, dz, mo.T0z);
-    mo.Txx = __builtin_fma(p2r2, sxx, mo.Txx);
-    mo.Tyy = __builtin_fma(p2r2, syy, mo.Tyy);
-    mo.Tzz = __builtin_fma(p2r2, szz, mo.Tzz);
-    mo.Txy = __builtin_fma(p2r2, sxy, mo.Txy);
-    mo.Txz = __builtin_fma(p2r2, sxz, mo.Txz);
-    mo.Tyz = __builtin_fma(p2r2, syz, mo.Tyz);
+    a.template fold<M, l>(mo);
   });
-  constexpr bool stash = sizeof(S) == 8;
+  constexpr bool stash = stash_n<M, S> > 0;
   if constexpr (stash) {
     static_for<STASH_BEGIN, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
@@ -244,25 +228,28 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
   mo.Tyz = add_partner(mo.Tyz);
   Frame fr;
   const unsigned fl = landau_frame(mo, fr);
-  const double tau = relaxation_time(rx, fr.n, fr.T);
-  EqCoef e = eq_coefficients(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
-  // odd classes (OEE, EOE, EEO, OOO) change sign for the inverse member
-  static_for<CLASS_BEGIN[1], CLASS_BEGIN[4]>([&](auto A) { e.c[decltype(A)::value] *= sg; });
-  e.c[29] *= sg;
+  const double tau = relaxation_time<M>(rx, fr.n, fr.T);
+  EqCoef<M> e = eq_coefficients<M>(fr.n, fr.T, fr.U0, fr.Ux, fr.Uy, fr.Uz);
+  // coefficients of spatially odd monomials change sign for the inverse member
+  static_for<0, M::NM>([&](auto A) {
+    constexpr int j = decltype(A)::value;
+    constexpr Mono mo_j = M::MONO[j];
+    if constexpr ((mo_j.ax + mo_j.ay + mo_j.az) % 2 != 0) e.c[j] *= sg;
+  });
   using CT = S;
   const double gdt = fr.U0 / tau;
   const CT gg = CT(gdt);
-  const double gs = gdt * INV_R * sg;
+  const double gs = gdt * M::INV_R * sg;
   const CT bx = CT(gs * fr.vx), by = CT(gs * fr.vy), bz = CT(gs * fr.vz);
   const int out_off = m * static_cast<int>(g.stride) + cell; // same for every point of this lane
-  static_for<0, NSHELL>([&](auto L) {
+  static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const ShellCoef<CT> s = shell_coefficients<l, CT>(e);
-    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+    const ShellCoef<M, CT> s = shell_coefficients<M, l, CT>(e);
+    static_for<shell_pair_begin<M>(l), shell_pair_begin<M>(l + 1)>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
+      constexpr Point P = M::P[2 * k];
       CT E, O;
-      shell_eval<2 * k, CT>(s, E, O);
+      shell_eval<M, 2 * k, CT>(s, E, O);
       const CT feq = CT(P.w) * (E + O);
       CT t = CT(0);
       if constexpr (P.tx != 0) t = fmadd(CT(P.tx), bx, t);
@@ -281,16 +268,15 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
 }
 
 
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
 k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
   constexpr int TB = pair_block<S>;
-  constexpr bool stash = sizeof(S) == 8;
-  __shared__ S lds[stash ? STASH_N : 1][TB];
+  __shared__ S lds[stash_rows<M, S>][TB];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
   unsigned flags = 0;
-  pair_cell_step<S, TB>(cur, nxt, g, rx, cell, lds, flags);
+  pair_cell_step<M, S, TB>(cur, nxt, g, rx, cell, lds, flags);
   if (flags) atomicOr(status, flags);
 }
 
@@ -316,7 +302,7 @@ inline constexpr int TUBE_BLOCK = 512; // one workgroup fills a CU at two waves 
 
 // One tube cell per lane (float32): the cell index is z, so each lane keeps
 // the 13 wrapped z offsets and every population base is wavefront-uniform.
-template <class S>
+template <class M, class S>
 __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__restrict__ out, const Geom &g,
                                                const Relax &rx, int z, unsigned &flags) {
   const bool active = z < g.cells;
@@ -324,30 +310,30 @@ __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__re
   int zo[2 * MAXD + 1];
 #pragma unroll
   for (int s = -MAXD; s <= MAXD; ++s) zo[s + MAXD] = wrap_back(zc, s, g.nz);
-  S f[Q];
-  static_for<0, Q>([&](auto I) {
+  S f[M::Q];
+  static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    constexpr Point P = D3Q128[i];
+    constexpr Point P = M::P[i];
     f[i] = load_at(in + i * g.stride, zo[P.tz + MAXD]);
   });
-  const Moments m = moments(f);
+  const Moments m = moments<M>(f);
   Frame fr;
   const unsigned fl = landau_frame(m, fr);
-  const double tau = relaxation_time(rx, fr.n, fr.T);
-  relax_cell(f, fr, tau, [&](auto I, S v) {
+  const double tau = relaxation_time<M>(rx, fr.n, fr.T);
+  relax_cell<M>(f, fr, tau, [&](auto I, S v) {
     constexpr int i = decltype(I)::value;
     if (active) store_at(out + i * g.stride, zc, v);
   });
   if (active) flags |= fl;
 }
 
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(TUBE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__restrict__ order,
         unsigned *__restrict__ status) {
   constexpr bool f64 = sizeof(S) == 8;
   constexpr int TB = TUBE_BLOCK;
-  __shared__ S lds[f64 ? STASH_N : 1][f64 ? TB : 1];
+  __shared__ S lds[stash_rows<M, S>][f64 ? TB : 1];
   const int j = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
   const TubeDesc d = desc[j]; // uniform: scalar loads
   Geom g;
@@ -371,9 +357,9 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
     S *out = base + (cur ? d.off[0] : d.off[1]);
     for (int c0 = 0; c0 < d.n; c0 += per_pass) {
       if constexpr (f64)
-        pair_cell_step<S, TB>(in, out, g, rx, c0 + slot, lds, flags);
+        pair_cell_step<M, S, TB>(in, out, g, rx, c0 + slot, lds, flags);
       else
-        tube_cell_step<S>(in, out, g, rx, c0 + slot, flags);
+        tube_cell_step<M, S>(in, out, g, rx, c0 + slot, flags);
     }
     __syncthreads();
     cur ^= 1;
@@ -390,7 +376,7 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
 // A lane owns a whole cell and uses the inversion pairs directly
 // (s = f_i + f_inv(i) for the even moments, d = f_i - f_inv(i) for the odd
 // ones, and f^eq = w (E +- O) for the two members).
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -409,22 +395,22 @@ k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, uns
     yo[sft + MAXD] = wrap_back(y, sft, g.ny) * g.nx;
     zo[sft + MAXD] = wrap_back(z, sft, g.nz) * static_cast<int>(nxny);
   }
-  S f[Q];
-  static_for<0, Q>([&](auto I) {
+  S f[M::Q];
+  static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    constexpr Point P = D3Q128[i];
+    constexpr Point P = M::P[i];
     f[i] = load_at(cur + (i * g.stride + yo[P.ty + MAXD] + zo[P.tz + MAXD]), xo[P.tx + MAXD]);
   });
   // keep the phases apart: interleaving them raises the register peak
   __builtin_amdgcn_sched_barrier(0);
-  const Moments m = moments(f);
+  const Moments m = moments<M>(f);
   __builtin_amdgcn_sched_barrier(0);
   Frame fr;
   const unsigned flags = landau_frame(m, fr);
-  const double tau = relaxation_time(rx, fr.n, fr.T);
+  const double tau = relaxation_time<M>(rx, fr.n, fr.T);
   __builtin_amdgcn_sched_barrier(0);
   const int own = static_cast<int>(row0) + x;
-  relax_cell(f, fr, tau, [&](auto I, S v) {
+  relax_cell<M>(f, fr, tau, [&](auto I, S v) {
     constexpr int i = decltype(I)::value;
     store_at(nxt + i * g.stride, own, v);
   });
@@ -433,7 +419,7 @@ k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, uns
 
 // Initial state: local equilibrium of (n, eps, v) in every cell, stored so
 // that the next gather returns it (scatter to x - theta_i).
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, const double *__restrict__ eps_,
                                                 const double *__restrict__ vx_, const double *__restrict__ vy_,
                                                 const double *__restrict__ vz_, S *__restrict__ cur, Geom g,
@@ -450,16 +436,16 @@ __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, c
   if (!__builtin_isfinite(n + eps + v2)) flags |= FLAG_NONFINITE;
   const double gamma = 1.0 / __builtin_sqrt(1.0 - v2);
   const double T = eps / (3.0 * n);
-  const EqCoef e = eq_coefficients(n, T, gamma, gamma * vx, gamma * vy, gamma * vz);
+  const EqCoef<M> e = eq_coefficients<M>(n, T, gamma, gamma * vx, gamma * vy, gamma * vz);
   using CT = double;
-  static_for<0, NSHELL>([&](auto L) {
+  static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
-    const ShellCoef<CT> s = shell_coefficients<l, CT>(e);
-    static_for<shell_pair_begin(l), shell_pair_begin(l + 1)>([&](auto K) {
+    const ShellCoef<M, CT> s = shell_coefficients<M, l, CT>(e);
+    static_for<shell_pair_begin<M>(l), shell_pair_begin<M>(l + 1)>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr Point P = D3Q128[2 * k];
+      constexpr Point P = M::P[2 * k];
       CT E, O;
-      shell_eval<2 * k, CT>(s, E, O);
+      shell_eval<M, 2 * k, CT>(s, E, O);
       store_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>(), S(P.w * (E + O)));
       store_at(cur + (2 * k + 1) * g.stride, sh.back<-P.tx, -P.ty, -P.tz>(), S(P.w * (E - O)));
     });
@@ -468,7 +454,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, c
 }
 
 // Macroscopic fields of the current pre-collision state.
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom g, double *__restrict__ n_,
                                                 double *__restrict__ eps_, double *__restrict__ U_,
                                                 double *__restrict__ P_, unsigned *__restrict__ status) {
@@ -477,9 +463,9 @@ __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom 
   int x, y, z;
   cell_coords(cell, g, x, y, z);
   const Shifts sh(x, y, z, g);
-  S f[Q];
-  gather(cur, g, sh, f);
-  const Moments m = moments(f);
+  S f[M::Q];
+  gather<M>(cur, g, sh, f);
+  const Moments m = moments<M>(f);
   Frame fr;
   const unsigned flags = landau_frame(m, fr);
   if (n_) n_[cell] = fr.n;

@@ -3,7 +3,7 @@ only: every step of the update runs in the HIP library).  PyTorch provides
 the device memory and the stream.
 
     from paper_1301_3423_amd import rlb
-    s = rlb.Solver(64, 64, 64, precision="fp64", eta_s=0.2)
+    s = rlb.Solver(64, 64, 64, precision="fp64", eta_s=0.2)   # order=2: Appendix A model
     s.init_fields(n, eps, vx, vy, vz)        # numpy (host) or torch (device)
     s.step(100)
     out = s.read_fields()                    # dict of numpy arrays
@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(PKG, "librlb.so")
 OK, EINVAL, ENOMEM, ENONPHYS, EHIP, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 TAU_FIXED, TAU_ETA_S = 0, 1
+ORDER3, ORDER2 = 3, 2
 FLAG_NONFINITE, FLAG_NONPHYSICAL, FLAG_LANDAU = 1, 2, 4
 MAX_Q = 128
 
@@ -56,7 +57,7 @@ class Lattice(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
-                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double), ("order", ctypes.c_int32)]
 
 
 class Tube(ctypes.Structure):
@@ -69,8 +70,8 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 class Request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("tau", ctypes.c_double),
-                ("eta_s", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("n", _DP), ("eps", _DP), ("vx", _DP), ("vy", _DP), ("vz", _DP),
                 ("out_n", _DP), ("out_eps", _DP), ("out_U4", _DP), ("out_P", _DP)]
 
@@ -91,8 +92,8 @@ def lib():
             raise RuntimeError("librlb.so is not built: run python -m paper_1301_3423_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64
-        L.rlb_lattice_info.argtypes = [ctypes.POINTER(Lattice)]
-        L.rlb_state_bytes.argtypes = [i32, i32, i32, i32]
+        L.rlb_lattice_info.argtypes = [i32, ctypes.POINTER(Lattice)]
+        L.rlb_state_bytes.argtypes = [i32, i32, i32, i32, i32]
         L.rlb_state_bytes.restype = ctypes.c_size_t
         L.rlb_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, vp]
         L.rlb_init_fields.argtypes = [vp, vp, vp, vp, vp, vp, i32]
@@ -104,9 +105,10 @@ def lib():
         L.rlb_load.argtypes = [vp, ctypes.c_char_p]
         L.rlb_destroy.argtypes = [vp]
         L.rlb_destroy.restype = None
-        L.rlb_batch_bytes.argtypes = [ctypes.POINTER(Tube), i32, i32]
+        L.rlb_batch_bytes.argtypes = [ctypes.POINTER(Tube), i32, i32, i32]
         L.rlb_batch_bytes.restype = ctypes.c_size_t
-        L.rlb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Tube), i32, i32, vp, ctypes.c_size_t, vp]
+        L.rlb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Tube), i32, i32, i32, vp, ctypes.c_size_t,
+                                       vp]
         L.rlb_batch_init.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32]
         L.rlb_batch_step.argtypes = [vp, ctypes.POINTER(i64)]
         L.rlb_batch_read.argtypes = [vp, i32, vp, vp, vp, vp, i32]
@@ -134,9 +136,9 @@ def check(rc):
     return rc
 
 
-def lattice_info():
+def lattice_info(order=ORDER3):
     lat = Lattice()
-    check(lib().rlb_lattice_info(ctypes.byref(lat)))
+    check(lib().rlb_lattice_info(int(order), ctypes.byref(lat)))
     q = lat.q
     return dict(q=q, r2=lat.r2, nshell=lat.nshell,
                 theta=np.array([[lat.theta[i][k] for k in range(3)] for i in range(q)], dtype=np.int64),
@@ -144,8 +146,8 @@ def lattice_info():
                 shell=np.array(lat.shell[:q]), sha256=lat.sha256.decode())
 
 
-def state_bytes(nx, ny, nz, precision="fp64"):
-    return lib().rlb_state_bytes(nx, ny, nz, _prec(precision))
+def state_bytes(nx, ny, nz, precision="fp64", order=ORDER3):
+    return lib().rlb_state_bytes(nx, ny, nz, _prec(precision), int(order))
 
 
 def _prec(p):
@@ -163,24 +165,27 @@ def _stream_ptr(stream):
 
 
 class Solver:
-    """One periodic nx x ny x nz box on the current HIP device.
+    """One periodic nx x ny x nz box on the current HIP device, third-order
+    (order=3) or second-order (order=2) model.
 
     Device memory is a torch uint8 tensor owned by this object; the solver
     runs on `stream` (default: torch's current stream at construction)."""
 
-    def __init__(self, nx, ny, nz, precision="fp64", tau=None, eta_s=None, stream=None, device=None):
+    def __init__(self, nx, ny, nz, precision="fp64", tau=None, eta_s=None, stream=None, device=None, order=ORDER3):
         import torch
         if (tau is None) == (eta_s is None):
             raise ValueError("give exactly one of tau, eta_s")
         self.shape = (nz, ny, nx)
         self.cells = nx * ny * nz
         self.precision = precision
+        self.order = int(order)
         cfg = Config(nx, ny, nz, _prec(precision), TAU_FIXED if tau is not None else TAU_ETA_S,
-                     float(tau) if tau is not None else 0.0, float(eta_s) if eta_s is not None else 0.0)
+                     float(tau) if tau is not None else 0.0, float(eta_s) if eta_s is not None else 0.0,
+                     self.order)
         self.cfg = cfg
-        nbytes = state_bytes(nx, ny, nz, precision)
+        nbytes = state_bytes(nx, ny, nz, precision, self.order)
         if nbytes == 0:
-            raise RLBError(EINVAL, "invalid lattice size or precision")
+            raise RLBError(EINVAL, "invalid lattice size, precision or order")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -258,28 +263,29 @@ def _tube_struct(t):
     return Tube(int(t["n"]), TAU_ETA_S, 0.0, float(t["eta_s"]))
 
 
-def batch_bytes(tubes, precision="fp64"):
+def batch_bytes(tubes, precision="fp64", order=ORDER3):
     arr = (Tube * len(tubes))(*[_tube_struct(t) for t in tubes])
-    return lib().rlb_batch_bytes(arr, len(tubes), _prec(precision))
+    return lib().rlb_batch_bytes(arr, len(tubes), _prec(precision), int(order))
 
 
 class Batch:
-    """Many independent 1 x 1 x n shock tubes of one precision, advanced
-    together by one persistent launch per step() call."""
+    """Many independent 1 x 1 x n shock tubes of one precision and one model,
+    advanced together by one persistent launch per step() call."""
 
-    def __init__(self, tubes, precision="fp64", stream=None, device=None):
+    def __init__(self, tubes, precision="fp64", stream=None, device=None, order=ORDER3):
         import torch
         self.tubes = [dict(t) for t in tubes]
         self.precision = precision
+        self.order = int(order)
         arr = (Tube * len(tubes))(*[_tube_struct(t) for t in tubes])
-        nbytes = lib().rlb_batch_bytes(arr, len(tubes), _prec(precision))
+        nbytes = lib().rlb_batch_bytes(arr, len(tubes), _prec(precision), self.order)
         if nbytes == 0:
             raise RLBError(EINVAL, "invalid tube list")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        check(lib().rlb_batch_create(ctypes.byref(h), arr, len(tubes), _prec(precision),
+        check(lib().rlb_batch_create(ctypes.byref(h), arr, len(tubes), _prec(precision), self.order,
                                      ctypes.c_void_p(self.buffer.data_ptr()), nbytes, _stream_ptr(self.stream)))
         self._h = h
 
@@ -324,7 +330,7 @@ def _dp(a):
     return a.ctypes.data_as(_DP) if a is not None else None
 
 
-def make_request(kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True):
+def make_request(kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True, order=ORDER3):
     """A Request plus the numpy arrays it points to (keep them alive)."""
     nx, ny, nz = shape
     if (tau is None) == (eta_s is None):
@@ -333,15 +339,17 @@ def make_request(kind, shape, precision, steps, fields, tau=None, eta_s=None, ou
     C = nx * ny * nz
     outs = dict(n=np.empty(C), eps=np.empty(C), U=np.empty((4, C)), P=np.empty(C)) if outputs else None
     r = Request(REQ_TUBE if kind == "tube" else REQ_BOX, nx, ny, nz, _prec(precision),
-                TAU_FIXED if tau is not None else TAU_ETA_S, float(tau or 0.0), float(eta_s or 0.0), int(steps),
+                TAU_FIXED if tau is not None else TAU_ETA_S, int(order), float(tau or 0.0), float(eta_s or 0.0),
+                int(steps),
                 *[_dp(a) for a in ins],
                 *([_dp(outs[k]) for k in ("n", "eps", "U", "P")] if outs else [None] * 4))
     return r, ins, outs
 
 
-def request_bytes(kind, shape, precision):
+def request_bytes(kind, shape, precision, order=ORDER3):
     nx, ny, nz = shape
-    r = Request(REQ_TUBE if kind == "tube" else REQ_BOX, nx, ny, nz, _prec(precision), TAU_FIXED, 1.0, 0.0, 0)
+    r = Request(REQ_TUBE if kind == "tube" else REQ_BOX, nx, ny, nz, _prec(precision), TAU_FIXED, int(order), 1.0,
+                0.0, 0)
     one = np.ones(1)
     r.n = r.eps = r.vx = r.vy = r.vz = _dp(one)
     return lib().rlb_request_bytes(ctypes.byref(r))
@@ -360,8 +368,8 @@ class Server:
         self._h = h
         self._live = {}      # id -> (request, inputs, outputs)
 
-    def submit(self, kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True):
-        r, ins, outs = make_request(kind, shape, precision, steps, fields, tau, eta_s, outputs)
+    def submit(self, kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True, order=ORDER3):
+        r, ins, outs = make_request(kind, shape, precision, steps, fields, tau, eta_s, outputs, order)
         rid = ctypes.c_int64()
         check(lib().rlb_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
         self._live[rid.value] = (r, outs)    # outputs stay alive until reported

@@ -38,16 +38,17 @@ def field_errors(gpu, ref):
     return out
 
 
-def run_pair(lat, shape, fields, steps, precision="fp64", **relax):
-    """Initialise both sides with the same fields, advance `steps`, read."""
+def run_pair(lat, shape, fields, steps, precision="fp64", order=3, **relax):
+    """Initialise both sides with the same fields, advance `steps`, read.
+    `lat` is the oracle lattice of model `order`."""
     nx, ny, nz = shape
-    note("case shape=%s steps=%d precision=%s relax=%s" % (shape, steps, precision, relax))
-    s = rlb.Solver(nx, ny, nz, precision=precision, **relax)
+    note("case order=%d shape=%s steps=%d precision=%s relax=%s" % (order, shape, steps, precision, relax))
+    s = rlb.Solver(nx, ny, nz, precision=precision, order=order, **relax)
     s.init_fields(*fields)
     s.step(steps)
     gpu = s.read_fields()
     flags, t = s.status()
-    o = orlb.Solver(nx, ny, nz, lat=lat, **relax)
+    o = orlb.Solver(nx, ny, nz, lat=lat, order=order, **relax)
     o.init_fields(*fields)
     o.step(steps)
     ref = o.read_fields()

@@ -40,14 +40,43 @@ def test_lattice_info_matches_table(lat):
     assert info["sha256"] == hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def test_state_bytes():
-    b64 = rlb.state_bytes(16, 16, 16, "fp64")
-    b32 = rlb.state_bytes(16, 16, 16, "mixed")
+def test_second_order_lattice_info_matches_table():
+    import hashlib
+    from oracle.lattice import model_lattice
+    lat2 = model_lattice(2)
+    info = rlb.lattice_info(rlb.ORDER2)
+    assert info["q"] == lat2.Q == 66 and info["r2"] == 9 and info["nshell"] == 3
+    for k in ("theta", "p0", "w", "inv", "shell"):
+        assert np.array_equal(info[k], getattr(lat2, k)), k
+    path = os.path.join(REPO, "paper_1301_3423_amd", "lattice", "d3q66.txt")
+    assert info["sha256"] == hashlib.sha256(open(path, "rb").read()).hexdigest()
+    # order 0 is the default, the third-order model
+    assert rlb.lattice_info(0)["q"] == 128
+    import ctypes
+    lat = rlb.Lattice()
+    assert rlb.lib().rlb_lattice_info(4, ctypes.byref(lat)) == rlb.EINVAL
+
+
+@pytest.mark.parametrize("order,q", [(3, 128), (2, 66)])
+def test_state_bytes(order, q):
+    b64 = rlb.state_bytes(16, 16, 16, "fp64", order)
+    b32 = rlb.state_bytes(16, 16, 16, "mixed", order)
     cells = 16 ** 3
-    assert b64 >= 2 * 128 * cells * 8 and b32 >= 2 * 128 * cells * 4
-    assert b64 - 2 * 128 * cells * 8 < 2 * 128 * 64 * 8 + 8192
+    assert b64 >= 2 * q * cells * 8 and b32 >= 2 * q * cells * 4
+    assert b64 - 2 * q * cells * 8 < 2 * q * 64 * 8 + 8192
     assert rlb.state_bytes(0, 4, 4) == 0
-    assert rlb.lib().rlb_state_bytes(4, 4, 4, 7) == 0
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 7, order) == 0
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, 1) == 0          # no first-order model
+
+
+def test_batch_and_request_bytes_follow_the_model():
+    tubes = [dict(n=100, tau=1.0), dict(n=37, eta_s=0.1)]
+    b3 = rlb.batch_bytes(tubes, "fp64", 3)
+    b2 = rlb.batch_bytes(tubes, "fp64", 2)
+    assert 0 < b2 < b3
+    assert rlb.batch_bytes(tubes, "fp64", 5) == 0
+    assert 0 < rlb.request_bytes("tube", (1, 1, 64), "mixed", 2) < rlb.request_bytes("tube", (1, 1, 64), "mixed", 3)
+    assert rlb.request_bytes("box", (8, 8, 8), "fp64", 9) == 0
 
 
 def test_strerror_names_codes():
@@ -71,4 +100,7 @@ def test_create_rejects_bad_arguments():
     assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
     cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_ETA_S, 0.0, -1.0)
     assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_FIXED, 1.0, 0.0, 1)   # order 1 does not exist
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    assert b"order" in L.rlb_last_error()
     assert L.rlb_step(None, 1) == rlb.EINVAL
