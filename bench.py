@@ -3,9 +3,10 @@
 Headline workload: a 256^3 periodic box in mixed precision (float32
 populations; moments, Landau frame and equilibrium coefficients in
 float64), smooth random fields with |v| <= 0.6 and eta/s = 0.5.  The same
-box is also timed in full float64.  A step is one launch of the fused
-gather-moments-Landau-equilibrium-collision kernel over every cell; inputs
-are resident in HBM before timing starts.
+box is also timed in full float64, and both precisions are timed again
+with the second-order model of Appendix A (66 points instead of 128).  A
+step is one launch of the fused gather-moments-Landau-equilibrium-collision
+kernel over every cell; inputs are resident in HBM before timing starts.
 
 Prints one JSON line (rank 0).  --gpus > 1 is not supported: the program
 runs on one GPU.
@@ -22,7 +23,14 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0
-Q = 128
+Q_OF_ORDER = {3: 128, 2: 66}
+
+
+def kernel_name(order, precision, edge):
+    """The step kernel the library launches for a box of this edge."""
+    if precision == "fp64":
+        return "k_step<Model<%d>, double>" % order
+    return ("k_step_row<Model<%d>, float>" if edge % 64 == 0 else "k_step<Model<%d>, float>") % order
 
 
 def parse():
@@ -36,6 +44,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tubes", action="store_true")
+    ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
@@ -117,9 +126,9 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def run_box(edge, precision, fields, steps, warmup, eta_s):
+def run_box(edge, precision, fields, steps, warmup, eta_s, order=3):
     from paper_1301_3423_amd import rlb
-    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order)
     s.init_fields(*fields)
     c0 = s.conserved()
     ms, wall = time_steps(s, steps, warmup)
@@ -128,7 +137,7 @@ def run_box(edge, precision, fields, steps, warmup, eta_s):
     read = s.read_fields()
     cells = edge ** 3
     b = 8 if precision == "fp64" else 4
-    bytes_per_launch = 2 * Q * b * cells
+    bytes_per_launch = 2 * Q_OF_ORDER[order] * b * cells
     out = dict(ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, wall_s=wall, flags=flags,
                achieved_gbs=bytes_per_launch / (ms * 1e-3) / 1e9, bytes_per_launch=bytes_per_launch,
                fields=read, t=t, conservation_drift=float(np.max(np.abs(c1 - c0)) / abs(c0[1])))
@@ -168,7 +177,7 @@ def run_tubes(precision, ntubes=512, steps=500, seed=4):
     ms = e0.elapsed_time(e1)
     lu = sum(t["N"] for t in spec) * steps
     flags = [b.status(j)[0] for j in range(len(spec))]
-    bpl = 2 * Q * (8 if precision == "fp64" else 4)
+    bpl = 2 * Q_OF_ORDER[3] * (8 if precision == "fp64" else 4)
     return dict(mlups=lu / (ms * 1e-3) / 1e6, ms=ms, cells=sum(t["N"] for t in spec),
                 achieved_gbs=lu * bpl / (ms * 1e-3) / 1e9, tubes_flagged=sum(1 for f in flags if f))
 
@@ -243,14 +252,20 @@ def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
 def run_riemann():
     """Latency of the 1D Riemann problems: the 1x1x200 tube (T 1.0 | 0.8,
     eta/s 0.1, 200 steps, FP64) and the paper's 1x1x1600 tube (T 1.0 | 0.5,
-    eta/s 0.5, 63 steps), each as one persistent launch, wall time from
-    submission of the launch to fields on the host."""
+    eta/s 0.5 and 0.1, t = 3.2 fm/c: 63 steps of the third-order model, 133
+    of the second-order one), each as one persistent launch, wall time from
+    submission of the launch to fields on the host; and the largest
+    difference between the two models' velocity profiles."""
     import torch
     from paper_1301_3423_amd import inputs, rlb
     out = {}
-    for name, n, tl, tr, es, steps in (("tube_200", 200, 1.0, 0.8, 0.1, 200),
-                                       ("paper_1600", 1600, 1.0, 0.5, 0.5, 63)):
-        b = rlb.Batch([dict(n=n, eta_s=es)], precision="fp64")
+    profiles = {}
+    for name, n, tl, tr, es, steps, order in (("tube_200", 200, 1.0, 0.8, 0.1, 200, 3),
+                                              ("paper_1600", 1600, 1.0, 0.5, 0.5, 63, 3),
+                                              ("paper_1600_eta0.1", 1600, 1.0, 0.5, 0.1, 63, 3),
+                                              ("paper_1600_order2", 1600, 1.0, 0.5, 0.5, 133, 2),
+                                              ("paper_1600_order2_eta0.1", 1600, 1.0, 0.5, 0.1, 133, 2)):
+        b = rlb.Batch([dict(n=n, eta_s=es)], precision="fp64", order=order)
         f = inputs.shock_tube(n, tl, tr)
         b.init_tube(0, *f)
         b.step(2)
@@ -260,10 +275,21 @@ def run_riemann():
         b.step(steps)
         r = b.read_tube(0)
         dt = time.perf_counter() - t0
-        out[name] = {"cells": n, "steps": steps, "wall_ms": round(dt * 1e3, 3),
-                     "max_vz": round(float(np.max(np.abs(r["U"][3] / r["U"][0]))), 4),
-                     "flags": b.status(0)[0]}
+        vz = r["U"][3] / r["U"][0]
+        profiles[name] = vz
+        out[name] = {"cells": n, "steps": steps, "order": order, "eta_s": es, "wall_ms": round(dt * 1e3, 3),
+                     "max_vz": round(float(np.max(np.abs(vz))), 4), "flags": b.status(0)[0]}
+    # the paper's second- vs third-order comparison at t = 3.2 fm/c (Figs. 4-5)
+    out["max_abs_dvz_3rd_vs_2nd"] = {
+        "eta_s_0.1": round(float(np.max(np.abs(profiles["paper_1600_eta0.1"] - profiles["paper_1600_order2_eta0.1"]))), 4),
+        "eta_s_0.5": round(float(np.max(np.abs(profiles["paper_1600"] - profiles["paper_1600_order2"]))), 4)}
     return out
+
+
+def roofline(r, kernel, edge):
+    return {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(kernel, edge),
+            "kernel": kernel, "algorithmic_bytes_per_launch": r["bytes_per_launch"]}
 
 
 def cpu_baseline(vmax, eta_s):
@@ -309,6 +335,16 @@ def main():
     if not args.no_fp64:
         fp64 = run_box(edge, "fp64", fields, args.steps, args.warmup, args.eta_s)
         print("bench: fp64 %.1f MLUPS" % fp64["mlups"], file=sys.stderr, flush=True)
+    second = {}
+    if not args.no_second_order:
+        for prec in ("mixed", "fp64"):
+            if prec == "fp64" and args.no_fp64:
+                continue
+            r = run_box(edge, prec, fields, args.steps, args.warmup, args.eta_s, order=2)
+            print("bench: second-order %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
+            second[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
+                            "roofline": roofline(r, kernel_name(2, prec, edge), edge),
+                            "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
     tubes = {}
     if not args.no_tubes:
         for prec in ("fp64", "mixed"):
@@ -324,7 +360,7 @@ def main():
         print("bench: serving p50 %.3f s p99 %.3f s, %.1f solves/s" % (
             serving["p50_latency_s"], serving["p99_latency_s"], serving["solves_per_s"]), file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.vmax, args.eta_s)
-    mixed_kernel = "k_step_row<float>" if edge % 64 == 0 else "k_step<float>"
+    mixed_kernel = kernel_name(3, "mixed", edge)
     line = {
         "metric": "MLUPS at 256^3 FP64 vs FP32-mixed (% HBM roofline); served p50/p99 latency",
         "value": round(mixed["mlups"], 2),
@@ -342,10 +378,7 @@ def main():
                                "moments/Landau frame), random fields |v|<=%.2g, T=1+-10%%, eta/s=%.2g"
                                % (edge, args.vmax, args.eta_s),
                    "cells": edge ** 3, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(mixed["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(mixed["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(mixed_kernel, edge),
-                     "kernel": mixed_kernel, "algorithmic_bytes_per_launch": mixed["bytes_per_launch"]},
+        "roofline": roofline(mixed, mixed_kernel, edge),
         "status_flags": mixed["flags"],
         "conservation_drift": mixed["conservation_drift"],
         "copy_GBps": round(copy_gbs, 1),
@@ -353,12 +386,7 @@ def main():
     if fp64 is not None:
         line["fp64"] = {"value": round(fp64["mlups"], 2), "unit": "MLUPS", "dtype": "f64",
                         "ms_per_step": round(fp64["ms_per_step"], 4),
-                        "roofline": {"bound": "hbm", "achieved": round(fp64["achieved_gbs"], 1),
-                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": round(fp64["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                                     "traffic": profiled_traffic("k_step<double>", edge),
-                                     "kernel": "k_step<double>",
-                                     "algorithmic_bytes_per_launch": fp64["bytes_per_launch"]},
+                        "roofline": roofline(fp64, kernel_name(3, "fp64", edge), edge),
                         "status_flags": fp64["flags"],
                         "conservation_drift": fp64["conservation_drift"],
                         "mixed_over_fp64": round(mixed["mlups"] / fp64["mlups"], 3)}
@@ -368,6 +396,9 @@ def main():
             "max_rel": field_error_summary(mixed["fields"], fp64["fields"]),
             "note": "max-norm relative error of the mixed path against the float64 GPU path at 256^3 "
                     "(the float64 path is pinned to the oracle at these sizes on sampled cells)"}
+    if second:
+        line["second_order"] = {"workload": "the same %d^3 box and fields with the second-order model of "
+                                            "Appendix A (66 points, R = 3)" % edge, **second}
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

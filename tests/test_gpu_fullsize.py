@@ -30,15 +30,20 @@ def _samples(edge, rng, count=6):
     return pts
 
 
-@pytest.mark.parametrize("edge,precision,vmax,eta_s,seed", [
-    (128, "fp64", 0.5, 0.2, 2),     # the 128^3 float64 configuration
-    (256, "fp64", 0.6, 0.5, 3),     # 256^3 float64 (timed next to the mixed one)
-    (256, "mixed", 0.6, 0.5, 3),    # the 256^3 mixed configuration
+@pytest.mark.parametrize("edge,precision,vmax,eta_s,seed,order", [
+    (128, "fp64", 0.5, 0.2, 2, 3),     # the 128^3 float64 configuration
+    (256, "fp64", 0.6, 0.5, 3, 3),     # 256^3 float64 (timed next to the mixed one)
+    (256, "mixed", 0.6, 0.5, 3, 3),    # the 256^3 mixed configuration
+    (256, "fp64", 0.6, 0.5, 3, 2),     # the same boxes with the second-order model
+    (256, "mixed", 0.6, 0.5, 3, 2),    # (displacements <= 3: the window is wider than needed)
 ])
-def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed):
-    note("full size %d^3 %s, %d steps" % (edge, precision, K))
+def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed, order):
+    from oracle.lattice import model_lattice
+    if order == 2:
+        lat = model_lattice(2)
+    note("full size %d^3 %s order %d, %d steps" % (edge, precision, order, K))
     fields = inputs.random_box(edge, edge, edge, vmax, seed)
-    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order)
     s.init_fields(*fields)
     s.step(K)
     out = s.read_fields()
@@ -50,7 +55,7 @@ def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed):
     worst = 0.0
     for c in _samples(edge, rng):
         win = [_window(a, c) for a in fields]
-        o = orlb.Solver(W, W, W, lat=lat, eta_s=eta_s)
+        o = orlb.Solver(W, W, W, lat=lat, eta_s=eta_s, order=order)
         o.init_fields(*win)
         o.step(K)
         ref = o.read_fields()

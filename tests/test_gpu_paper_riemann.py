@@ -6,7 +6,14 @@ batch path is compared with the oracle; raising the reference temperature
 reproduces the onset of instability the paper reports qualitatively (its
 bound, T > 4, belongs to its own quadrature table, which is not available:
 for the recomputed table the bound is lower, and both sides must agree on
-which runs fail)."""
+which runs fail).
+
+The same problem with the second-order model of Appendix A: one step is
+delta t = R delta x = 0.024 fm/c there (Sec. III), so t = 3.2 fm/c is 133
+steps.  The paper reads its Figs. 4-5 as: the two models nearly agree at
+eta/s = 0.1 and part ways at eta/s = 0.5; the comparison below checks that
+ordering of the differences between the two models' velocity profiles (no
+BAMPS data exist to compare either with)."""
 import numpy as np
 import pytest
 
@@ -17,6 +24,7 @@ from paper_1301_3423_amd import inputs, rlb
 pytestmark = pytest.mark.gpu
 
 N, STEPS = 1600, 63
+STEPS_2ND = 133          # 3.2 / 0.024
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -58,3 +66,40 @@ def test_reference_temperature_stability_agrees_with_oracle(lat):
         note("T_ref %.1f: oracle flags %d, gpu flags %d" % (T, oflags, gflags))
         assert (oflags == 0) == (gflags == 0)
     assert b.status(0)[0] == 0 and b.status(1)[0] == 0      # T_ref 1 and 2.5 stay physical
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paper_riemann_problem_second_order(precision):
+    from oracle.lattice import model_lattice
+    lat2 = model_lattice(2)
+    tubes = [dict(n=N, eta_s=0.1), dict(n=N, eta_s=0.5)]
+    b = rlb.Batch(tubes, precision=precision, order=2)
+    f = inputs.shock_tube(N, 1.0, 0.5)
+    for j in range(2):
+        b.init_tube(j, *f)
+    b.step(STEPS_2ND)
+    for j, t in enumerate(tubes):
+        o = orlb.Solver(1, 1, N, lat=lat2, eta_s=t["eta_s"], order=2)
+        o.init_fields(*f)
+        o.step(STEPS_2ND)
+        err = field_errors(b.read_tube(j), o.read_fields())
+        note("second order eta/s %.1f %s: max err %.2e" % (t["eta_s"], precision, max(err.values())))
+        assert b.status(j)[0] == 0
+        assert max(err.values()) <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_second_and_third_order_differ_more_at_high_viscosity():
+    """max_z |v_3rd - v_2nd| at t = 3.2 fm/c, GPU FP64, both models."""
+    f = inputs.shock_tube(N, 1.0, 0.5)
+    v = {}
+    for order, steps in ((3, STEPS), (2, STEPS_2ND)):
+        b = rlb.Batch([dict(n=N, eta_s=0.1), dict(n=N, eta_s=0.5)], precision="fp64", order=order)
+        for j in range(2):
+            b.init_tube(j, *f)
+        b.step(steps)
+        for j, es in enumerate((0.1, 0.5)):
+            r = b.read_tube(j)
+            v[(order, es)] = r["U"][3] / r["U"][0]
+    d = {es: float(np.max(np.abs(v[(3, es)] - v[(2, es)]))) for es in (0.1, 0.5)}
+    note("max |v_3rd - v_2nd|: eta/s 0.1 %.4f, eta/s 0.5 %.4f" % (d[0.1], d[0.5]))
+    assert d[0.5] > 2 * d[0.1]
