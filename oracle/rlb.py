@@ -17,6 +17,12 @@ One step, for every cell x, in the paper's order:
 Arrays: populations f[Q, nz, ny, nx] (x fastest), the same ordering the
 library stores on the device.
 
+Solid walls (optional): the paper asks for inversion-paired weights
+(w_i = w_inv(i), Sec. II C) so that bounce-back can impose zero velocity on
+solid walls.  A solid cell holds no fluid; a population i whose source
+cell x - theta_i is solid is replaced by the post-collision population of
+the inverse direction at x itself (link-wise bounce-back, stream_with_walls).
+
 Two models share these steps: the third-order model (order 3: 128 points,
 R = sqrt(41), J_0..J_29) and the second-order model of Appendix A (order 2:
 66 points, R = 3, J_0..J_13, Eq. equi2nd).  They differ in the lattice, the
@@ -100,6 +106,21 @@ def stream(lat, f4):
     return out
 
 
+def stream_with_walls(lat, f4, solid):
+    """Step 7 with solid cells solid[nz, ny, nx] (bool): for every fluid
+    cell x, f_new_i(x) = f_post_i(x - theta_i) if x - theta_i is fluid,
+    else f_post_inv(i)(x) (the population that would have entered the wall
+    comes back reversed, on the same shell).  Solid cells hold zeros."""
+    out = np.empty_like(f4)
+    for i in range(lat.Q):
+        tx, ty, tz = (int(t) for t in lat.theta[i])
+        moved = np.roll(f4[i], shift=(tz, ty, tx), axis=(0, 1, 2))
+        source_solid = np.roll(solid, shift=(tz, ty, tx), axis=(0, 1, 2))     # solid at x - theta_i
+        out[i] = np.where(source_solid, f4[lat.inv[i]], moved)
+    out[:, solid] = 0.0
+    return out
+
+
 def equilibrium_state(eq, n, eps, vx, vy, vz):
     """Populations at local equilibrium for given n, eps, v (used for
     initial conditions, Sec. III): T = eps / (3 n), U = gamma (1, v)."""
@@ -114,9 +135,10 @@ def equilibrium_state(eq, n, eps, vx, vy, vz):
 
 class Solver:
     """A periodic nx x ny x nz lattice advanced by Eq. rlb:disc, with the
-    third-order (order=3) or the second-order (order=2) model."""
+    third-order (order=3) or the second-order (order=2) model, optionally
+    with solid cells (solid: bool array [nz, ny, nx], bounce-back walls)."""
 
-    def __init__(self, nx, ny, nz, tau=None, eta_s=None, lat=None, kmax=None, order=3):
+    def __init__(self, nx, ny, nz, tau=None, eta_s=None, lat=None, kmax=None, order=3, solid=None):
         if (tau is None) == (eta_s is None):
             raise ValueError("give exactly one of tau, eta_s")
         if order not in KMAX:
@@ -127,6 +149,11 @@ class Solver:
         self.shape = (nz, ny, nx)
         self.C = nx * ny * nz
         self.tau, self.eta_s = tau, eta_s
+        self.solid = None
+        if solid is not None:
+            self.solid = np.asarray(solid, dtype=bool).reshape(self.shape)
+            if self.solid.all():
+                raise ValueError("no fluid cell")
         self.f = None
         self.t = 0
         self.flags = 0
@@ -134,25 +161,42 @@ class Solver:
     def init_fields(self, n, eps, vx, vy, vz):
         f2 = equilibrium_state(self.eq, n, eps, vx, vy, vz)
         self.f = f2.reshape((self.lat.Q,) + self.shape)
+        if self.solid is not None:
+            self.f[:, self.solid] = 0.0
         self.t = 0
 
+    def _fluid(self):
+        return np.ones(self.C, dtype=bool) if self.solid is None else ~self.solid.ravel()
+
     def step(self, nsteps=1):
+        fluid = self._fluid()
         for _ in range(nsteps):
             f2 = self.f.reshape(self.lat.Q, self.C)
-            fs, mac = collide(self.lat, self.eq, f2, self.tau, self.eta_s, self.order)
+            fs = np.zeros_like(f2)
+            fs[:, fluid], mac = collide(self.lat, self.eq, f2[:, fluid], self.tau, self.eta_s, self.order)
             self.flags |= mac["flags"]
-            self.f = stream(self.lat, fs.reshape(self.f.shape))
+            fs = fs.reshape(self.f.shape)
+            self.f = stream(self.lat, fs) if self.solid is None else stream_with_walls(self.lat, fs, self.solid)
             self.t += 1
 
     def read_fields(self):
-        """n, eps, U[4, C], P of the current (pre-collision) state."""
-        mac = macroscopic(self.lat, self.f.reshape(self.lat.Q, self.C))
-        return dict(n=mac["n"], eps=mac["eps"], U=mac["U"].T.copy(), P=mac["P"],
-                    T=mac["T"], flags=mac["flags"] | self.flags)
+        """n, eps, U[4, C], P of the current (pre-collision) state; zero at
+        solid cells."""
+        fluid = self._fluid()
+        mac = macroscopic(self.lat, self.f.reshape(self.lat.Q, self.C)[:, fluid])
+        out = dict(n=np.zeros(self.C), eps=np.zeros(self.C), U=np.zeros((4, self.C)), P=np.zeros(self.C),
+                   T=np.zeros(self.C))
+        for k in ("n", "eps", "P", "T"):
+            out[k][fluid] = mac[k]
+        out["U"][:, fluid] = mac["U"].T
+        out["flags"] = mac["flags"] | self.flags
+        return out
 
     def conserved(self):
         """Box totals of N^0 and T^{0 nu} (the quantities the collision
-        keeps per cell and the streaming keeps globally)."""
+        keeps per cell and the streaming keeps globally; with walls, N^0 and
+        T^{00} stay and the walls exchange momentum).  Solid cells hold
+        zeros, so the sum runs over the fluid."""
         f2 = self.f.reshape(self.lat.Q, self.C)
         tot = f2.sum(axis=1)                                     # per population
         p = self.lat.p

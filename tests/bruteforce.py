@@ -26,8 +26,12 @@ def landau_eig(Tm):
     raise RuntimeError("no timelike eigenvector")
 
 
-def step(lat, f, shape, tau=None, eta_s=None, order=3):
+def step(lat, f, shape, tau=None, eta_s=None, order=3, solid=None):
     """f[Q][nz][ny][nx] (numpy) -> new array after collide + push.
+    solid[z][y][x] (optional): solid cells are skipped and hold zeros; a
+    post-collision population pushed into a solid cell is pushed back into
+    its own cell as the inverse population (found by searching the table
+    for -theta on the same shell).
     eta/s gives tau through eta = (2/3) n T (tau - 1/2) / R (Sec. III) for
     the third-order model and eta = (1/7) n T (tau - 1/2) / R (Appendix A)
     for the second-order one."""
@@ -37,9 +41,17 @@ def step(lat, f, shape, tau=None, eta_s=None, order=3):
     nz, ny, nx = shape
     Q = lat.Q
     out = np.zeros_like(f)
+    def inverse(i):
+        for j in range(Q):
+            if lat.shell[j] == lat.shell[i] and all(lat.theta[j][k] == -lat.theta[i][k] for k in range(3)):
+                return j
+        raise RuntimeError("no inverse")
+    inv = [inverse(i) for i in range(Q)]
     for z in range(nz):
         for y in range(ny):
             for x in range(nx):
+                if solid is not None and solid[z][y][x]:
+                    continue
                 fc = [f[i, z, y, x] for i in range(Q)]
                 N = np.zeros(4)
                 Tm = np.zeros((4, 4))
@@ -58,5 +70,9 @@ def step(lat, f, shape, tau=None, eta_s=None, order=3):
                     pU = lat.p[i] @ ETA @ U
                     fs = fc[i] - pU / (t * lat.p[i, 0]) * (fc[i] - feq)
                     tx, ty, tz = (int(a) for a in lat.theta[i])
-                    out[i, (z + tz) % nz, (y + ty) % ny, (x + tx) % nx] = fs
+                    zz, yy, xx = (z + tz) % nz, (y + ty) % ny, (x + tx) % nx
+                    if solid is not None and solid[zz][yy][xx]:
+                        out[inv[i], z, y, x] = fs
+                    else:
+                        out[i, zz, yy, xx] = fs
     return out
