@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tubes", action="store_true")
     ap.add_argument("--no-second-order", action="store_true")
+    ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
@@ -126,9 +127,11 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def run_box(edge, precision, fields, steps, warmup, eta_s, order=3):
+def run_box(edge, precision, fields, steps, warmup, eta_s, order=3, solid=None):
     from paper_1301_3423_amd import rlb
     s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order)
+    if solid is not None:
+        s.set_walls(solid)
     s.init_fields(*fields)
     c0 = s.conserved()
     ms, wall = time_steps(s, steps, warmup)
@@ -140,7 +143,8 @@ def run_box(edge, precision, fields, steps, warmup, eta_s, order=3):
     bytes_per_launch = 2 * Q_OF_ORDER[order] * b * cells
     out = dict(ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, wall_s=wall, flags=flags,
                achieved_gbs=bytes_per_launch / (ms * 1e-3) / 1e9, bytes_per_launch=bytes_per_launch,
-               fields=read, t=t, conservation_drift=float(np.max(np.abs(c1 - c0)) / abs(c0[1])))
+               fields=read, t=t, conservation_drift=float(np.max(np.abs(c1 - c0)) / abs(c0[1])),
+               conservation_drift_N0=float(abs(c1[0] - c0[0]) / abs(c0[0])))
     del s
     return out
 
@@ -345,6 +349,22 @@ def main():
             second[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
                             "roofline": roofline(r, kernel_name(2, prec, edge), edge),
                             "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
+    walls = None
+    if not args.no_walls:
+        # a channel: solid slabs of 6 cells (the largest displacement) at both y ends
+        solid = np.zeros((edge, edge, edge), dtype=bool)
+        solid[:, :6, :] = True
+        solid[:, -6:, :] = True
+        fluid = int((~solid).sum())
+        r = run_box(edge, "mixed", fields, args.steps, args.warmup, args.eta_s, solid=solid)
+        print("bench: walls mixed %.1f MLUPS" % r["mlups"], file=sys.stderr, flush=True)
+        walls = {"workload": "the same %d^3 box as a channel: solid slabs of 6 cells at both y ends (%.1f%% "
+                             "solid), link-wise bounce-back, mixed precision, third order"
+                             % (edge, 100.0 * (1 - fluid / edge ** 3)),
+                 "value": round(r["mlups"], 2), "unit": "MLUPS (all cells)",
+                 "fluid_mlups": round(r["mlups"] * fluid / edge ** 3, 2), "ms_per_step": round(r["ms_per_step"], 4),
+                 "vs_periodic": round(r["ms_per_step"] / mixed["ms_per_step"], 3),
+                 "status_flags": r["flags"], "N0_drift": r["conservation_drift_N0"]}
     tubes = {}
     if not args.no_tubes:
         for prec in ("fp64", "mixed"):
@@ -399,6 +419,8 @@ def main():
     if second:
         line["second_order"] = {"workload": "the same %d^3 box and fields with the second-order model of "
                                             "Appendix A (66 points, R = 3)" % edge, **second}
+    if walls is not None:
+        line["walls"] = walls
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

@@ -183,6 +183,34 @@ int rlb_load(rlb_solver *s, const char *path);
 /* Releases the solver's host allocations (not the caller's buffer). */
 void rlb_destroy(rlb_solver *s);
 
+/* ---- solid walls ------------------------------------------------------------
+ * The paper asks for weights that are equal on inversion pairs so that
+ * bounce-back can impose zero velocity on solid walls (Sec. II C).  The
+ * library implements link-wise bounce-back: a population i whose source cell
+ * x - theta_i is solid arrives at fluid cell x as the post-collision value of
+ * the inverse population at x.  N^0 and T^{00} stay conserved; the walls
+ * exchange momentum with the fluid.  solid[] holds nx*ny*nz bytes, x
+ * fastest, non-zero = solid.  A population can jump over a wall thinner than
+ * its displacement (up to 6 cells in the third-order model, 3 in the
+ * second-order one), so walls meant to be impermeable must be at least that
+ * thick.  Solid cells hold no fluid: rlb_read_fields reports zeros there, and
+ * a cell that becomes solid loses its contents. */
+
+/* Device bytes the walls of this mask need (the mask plus one 12-byte
+ * bounce-back link per solid-cell/population pair that points into fluid);
+ * 0 if the arguments are invalid or every cell is solid.  Pure host
+ * function. */
+size_t rlb_walls_bytes(int32_t order, int32_t nx, int32_t ny, int32_t nz, const uint8_t *solid);
+
+/* Sets (solid != NULL) or removes (solid == NULL) the walls of a solver.
+ * d_buf: caller-owned device memory of >= rlb_walls_bytes bytes, 256-byte
+ * aligned, kept alive while the walls are set; the host mask may be released
+ * when the call returns (it synchronises the solver's stream).  Takes effect
+ * from the next step; rlb_save records the mask's hash and rlb_load requires
+ * the same walls.  Errors: RLB_EINVAL (NULL solver or buffer, misaligned,
+ * every cell solid), RLB_ENOMEM (buffer too small), RLB_EHIP. */
+int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes);
+
 /* ---- many independent shock tubes (1 x 1 x n periodic lattices) ------------
  * The Riemann problems of Sec. III are one-dimensional: a tube is a periodic
  * 1 x 1 x n lattice on which only the z displacement of each point moves

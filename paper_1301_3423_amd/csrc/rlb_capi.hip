@@ -36,6 +36,8 @@ constexpr size_t PAD_BYTES = 256;
 
 size_t elem_bytes(int precision) { return precision == RLB_MIXED ? 4 : 8; }
 
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
 // Elements between consecutive population arrays: the cell count rounded up
 // to 256 bytes, plus 256 bytes, so that the arrays do not all start at the
 // same offset modulo a large power of two.
@@ -80,6 +82,11 @@ struct rlb_solver {
   int cur;
   int64_t t;
   bool initialized;
+  // solid walls (rlb_set_walls): mask and bounce-back links in caller memory
+  const uint8_t *d_solid = nullptr;
+  const rlb::Link *d_links = nullptr;
+  int64_t nlinks = 0;
+  uint64_t solid_hash = 0; // FNV-1a of the mask, 0 without walls
 };
 
 namespace {
@@ -104,28 +111,50 @@ rlb::Relax relax_of(const rlb_solver *s) {
 
 unsigned grid_of(int64_t cells) { return static_cast<unsigned>((cells + rlb::BLOCK - 1) / rlb::BLOCK); }
 
+// The step kernels of one box, with or without walls.
+template <class M, bool WALLS>
+void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r) {
+  const uint8_t *solid = WALLS ? s->d_solid : nullptr;
+  if (s->cfg.precision == RLB_FP64) {
+    constexpr int TB = rlb::pair_block<double>;
+    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
+    rlb::k_step<M, double, WALLS><<<grid, block, 0, s->stream>>>(
+        static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+  } else if (s->cfg.nx % 64 == 0) {
+    const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
+    rlb::k_step_row<M, float, WALLS><<<grid, block, 0, s->stream>>>(
+        static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+  } else {
+    constexpr int TB = rlb::pair_block<float>;
+    const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
+    rlb::k_step<M, float, WALLS><<<grid, block, 0, s->stream>>>(
+        static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+  }
+  if constexpr (WALLS) {
+    if (s->nlinks > 0) {
+      const dim3 grid(static_cast<unsigned>((s->nlinks + rlb::BLOCK - 1) / rlb::BLOCK)), block(rlb::BLOCK);
+      if (s->cfg.precision == RLB_FP64)
+        rlb::k_bounce<double><<<grid, block, 0, s->stream>>>(static_cast<double *>(s->buf[1 - s->cur]), s->d_links,
+                                                             s->nlinks, s->stride);
+      else
+        rlb::k_bounce<float><<<grid, block, 0, s->stream>>>(static_cast<float *>(s->buf[1 - s->cur]), s->d_links,
+                                                            s->nlinks, s->stride);
+    }
+  }
+}
+
 // float64: the two-lane kernel; float32: one lane per cell when rows are
-// whole wavefronts (nx % 64 == 0), else the two-lane kernel.
+// whole wavefronts (nx % 64 == 0), else the two-lane kernel; with walls, the
+// bounce-back copies follow on the same stream.
 int launch_step(rlb_solver *s) {
   const rlb::Geom g = geom_of(s);
   const rlb::Relax r = relax_of(s);
   with_model(s->cfg.order, [&](auto m) {
     using M = decltype(m);
-    if (s->cfg.precision == RLB_FP64) {
-      constexpr int TB = rlb::pair_block<double>;
-      const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-      rlb::k_step<M, double><<<grid, block, 0, s->stream>>>(static_cast<const double *>(s->buf[s->cur]),
-                                                            static_cast<double *>(s->buf[1 - s->cur]), g, r, s->status);
-    } else if (s->cfg.nx % 64 == 0) {
-      const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
-      rlb::k_step_row<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]),
-                                                               static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status);
-    } else {
-      constexpr int TB = rlb::pair_block<float>;
-      const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-      rlb::k_step<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]),
-                                                           static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status);
-    }
+    if (s->d_solid)
+      launch_step_kernels<M, true>(s, g, r);
+    else
+      launch_step_kernels<M, false>(s, g, r);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -315,10 +344,10 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
     using M = decltype(m);
     if (s->cfg.precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, s->stream>>>(static_cast<const double *>(s->buf[s->cur]), g, dn, de, dU,
-                                                            dP, s->status);
+                                                            dP, s->status, s->d_solid);
     else
       rlb::k_read<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]), g, dn, de, dU,
-                                                           dP, s->status);
+                                                           dP, s->status, s->d_solid);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -333,9 +362,44 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
   return RLB_OK;
 }
 
+namespace {
+// Box totals with walls: per-cell N^0 and T^{0 nu} into the idle buffer,
+// then the fixed-order two-pass reduction over those five arrays.
+int conserved_walls(rlb_solver *s, double out[5]) {
+  const rlb::Geom g = geom_of(s);
+  const int64_t C = s->cells;
+  double *cellv = static_cast<double *>(s->buf[1 - s->cur]); // 5 C doubles
+  const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
+  const int nblocks = static_cast<int>((C + chunk - 1) / chunk);
+  double *partial = cellv + 5 * C;
+  double *total = partial + 5 * static_cast<size_t>(nblocks);
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    if (s->cfg.precision == RLB_FP64)
+      rlb::k_cell_conserved<M, double><<<dim3(grid_of(C)), dim3(rlb::BLOCK), 0, s->stream>>>(
+          static_cast<const double *>(s->buf[s->cur]), g, s->d_solid, cellv);
+    else
+      rlb::k_cell_conserved<M, float><<<dim3(grid_of(C)), dim3(rlb::BLOCK), 0, s->stream>>>(
+          static_cast<const float *>(s->buf[s->cur]), g, s->d_solid, cellv);
+    return 0;
+  });
+  rlb::Geom rows = g;
+  rows.stride = C; // five rows of C values
+  hipLaunchKernelGGL(rlb::k_popsum_partial<double>, dim3(nblocks, 5), dim3(rlb::BLOCK), 0, s->stream, cellv, rows,
+                     partial, nblocks);
+  hipLaunchKernelGGL(rlb::k_popsum_final, dim3(5), dim3(rlb::BLOCK), 0, s->stream, partial, nblocks, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "conserved (walls) launch");
+  RLB_HIP(hipMemcpyAsync(out, total, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  RLB_HIP(hipStreamSynchronize(s->stream));
+  return RLB_OK;
+}
+} // namespace
+
 int rlb_conserved(rlb_solver *s, double out[5]) {
   if (!s || !out) return fail(RLB_EINVAL, "rlb_conserved: NULL argument");
   if (!s->initialized) return fail(RLB_ESTATE, "rlb_conserved: call rlb_init_fields first");
+  if (s->d_solid) return conserved_walls(s, out);
   const rlb::Geom g = geom_of(s);
   const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
   const int nblocks = static_cast<int>((s->cells + chunk - 1) / chunk);
@@ -382,8 +446,9 @@ int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t) {
 }
 
 namespace {
-// version 2: the configuration carries the model order
-constexpr int32_t CKPT_VERSION = 2;
+// version 3: the configuration carries the model order, and the header the
+// hash of the solid mask (0 without walls)
+constexpr int32_t CKPT_VERSION = 3;
 struct CkptHeader {
   char magic[8];
   int32_t version;
@@ -392,6 +457,7 @@ struct CkptHeader {
   uint32_t flags;
   int32_t q;
   char sha256[65];
+  uint64_t solid_hash;
 };
 } // namespace
 
@@ -404,6 +470,7 @@ int rlb_save(rlb_solver *s, const char *path) {
   h.cfg = s->cfg;
   h.t = s->t;
   h.q = q_of(s->cfg.order);
+  h.solid_hash = s->solid_hash;
   rlb_lattice_t lat;
   rlb_lattice_info(s->cfg.order, &lat);
   std::memcpy(h.sha256, lat.sha256, sizeof(h.sha256));
@@ -439,7 +506,8 @@ int rlb_load(rlb_solver *s, const char *path) {
   if (std::memcmp(h.magic, "RLBCKPT1", 8) != 0 || h.version != CKPT_VERSION || h.q != Q ||
       std::memcmp(h.sha256, lat.sha256, 64) != 0 || h.cfg.nx != s->cfg.nx || h.cfg.ny != s->cfg.ny ||
       h.cfg.nz != s->cfg.nz || h.cfg.precision != s->cfg.precision || h.cfg.tau_mode != s->cfg.tau_mode ||
-      h.cfg.tau != s->cfg.tau || h.cfg.eta_s != s->cfg.eta_s || h.cfg.order != s->cfg.order) {
+      h.cfg.tau != s->cfg.tau || h.cfg.eta_s != s->cfg.eta_s || h.cfg.order != s->cfg.order ||
+      h.solid_hash != s->solid_hash) {
     std::fclose(fp);
     return fail(RLB_EINVAL, "rlb_load: checkpoint does not match this solver");
   }
@@ -454,6 +522,106 @@ int rlb_load(rlb_solver *s, const char *path) {
   RLB_HIP(hipStreamSynchronize(s->stream));
   s->t = h.t;
   s->initialized = true;
+  return RLB_OK;
+}
+
+// ---- solid walls ---------------------------------------------------------------
+
+} // extern "C"
+
+namespace {
+
+uint64_t fnv1a(const uint8_t *p, int64_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t i = 0; i < n; ++i) {
+    h ^= p[i] ? 1u : 0u; // the mask's meaning, not its byte values
+    h *= 1099511628211ull;
+  }
+  return h ? h : 1;
+}
+
+// Bounce-back links of a mask: for every solid cell s and population i
+// whose target s + theta_i is fluid, (s, s + theta_i, i); grouped by
+// population, cells ascending.  Returns false if no cell is fluid.
+template <class M>
+bool build_links(int nx, int ny, int nz, const uint8_t *solid, std::vector<rlb::Link> *links, int64_t *count) {
+  const int64_t C = static_cast<int64_t>(nx) * ny * nz;
+  bool any_fluid = false;
+  for (int64_t c = 0; c < C && !any_fluid; ++c) any_fluid = solid[c] == 0;
+  if (!any_fluid) return false;
+  int64_t n = 0;
+  for (int i = 0; i < M::Q; ++i) {
+    const rlb::Point &p = M::P[i];
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t sc = x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z);
+          if (!solid[sc]) continue;
+          const int xt = ((x + p.tx) % nx + nx) % nx, yt = ((y + p.ty) % ny + ny) % ny, zt = ((z + p.tz) % nz + nz) % nz;
+          const int64_t tc = xt + static_cast<int64_t>(nx) * (yt + static_cast<int64_t>(ny) * zt);
+          if (solid[tc]) continue;
+          if (links) links->push_back(rlb::Link{static_cast<int32_t>(sc), static_cast<int32_t>(tc), i});
+          ++n;
+        }
+  }
+  *count = n;
+  return true;
+}
+
+size_t walls_bytes_for(int64_t cells, int64_t nlinks) {
+  return align256(static_cast<size_t>(cells)) + align256(static_cast<size_t>(nlinks) * sizeof(rlb::Link));
+}
+
+} // namespace
+
+extern "C" {
+
+size_t rlb_walls_bytes(int32_t order, int32_t nx, int32_t ny, int32_t nz, const uint8_t *solid) {
+  if (!solid || !valid_dims(nx, ny, nz) || !valid_order(order)) return 0;
+  int64_t n = 0;
+  const bool ok = with_model(norm_order(order), [&](auto m) {
+    using M = decltype(m);
+    return build_links<M>(nx, ny, nz, solid, nullptr, &n);
+  });
+  if (!ok) return 0;
+  return walls_bytes_for(static_cast<int64_t>(nx) * ny * nz, n);
+}
+
+int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes) {
+  if (!s) return fail(RLB_EINVAL, "rlb_set_walls: NULL solver");
+  if (!solid) {
+    s->d_solid = nullptr;
+    s->d_links = nullptr;
+    s->nlinks = 0;
+    s->solid_hash = 0;
+    return RLB_OK;
+  }
+  if (!d_buf) return fail(RLB_EINVAL, "rlb_set_walls: NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_set_walls: buffer not 256-byte aligned");
+  std::vector<rlb::Link> links;
+  int64_t n = 0;
+  const bool ok = with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    return build_links<M>(s->cfg.nx, s->cfg.ny, s->cfg.nz, solid, &links, &n);
+  });
+  if (!ok) return fail(RLB_EINVAL, "rlb_set_walls: every cell is solid");
+  const size_t need = walls_bytes_for(s->cells, n);
+  if (bytes < need)
+    return fail(RLB_ENOMEM, "rlb_set_walls: buffer has " + std::to_string(bytes) + " bytes, needs " + std::to_string(need));
+  char *p = static_cast<char *>(d_buf);
+  uint8_t *d_solid = reinterpret_cast<uint8_t *>(p);
+  rlb::Link *d_links = reinterpret_cast<rlb::Link *>(p + align256(static_cast<size_t>(s->cells)));
+  // the mask as 0/1 bytes
+  std::vector<uint8_t> mask(static_cast<size_t>(s->cells));
+  for (int64_t c = 0; c < s->cells; ++c) mask[c] = solid[c] ? 1 : 0;
+  RLB_HIP(hipMemcpyAsync(d_solid, mask.data(), mask.size(), hipMemcpyHostToDevice, s->stream));
+  if (n > 0)
+    RLB_HIP(hipMemcpyAsync(d_links, links.data(), links.size() * sizeof(rlb::Link), hipMemcpyHostToDevice, s->stream));
+  RLB_HIP(hipStreamSynchronize(s->stream));
+  s->d_solid = d_solid;
+  s->d_links = d_links;
+  s->nlinks = n;
+  s->solid_hash = fnv1a(mask.data(), s->cells);
   return RLB_OK;
 }
 
@@ -485,8 +653,6 @@ struct rlb_batch {
 };
 
 namespace {
-
-size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool valid_tube(const rlb_tube &tb) {
   if (tb.n < 1 || tb.n > (1 << 27)) return false;
@@ -733,10 +899,10 @@ int rlb_batch_read(rlb_batch *b, int32_t tube, double *n, double *eps, double *U
     using M = decltype(m);
     if (b->precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, b->stream>>>(static_cast<const double *>(tube_buf(b, tube, cur)), g, dn,
-                                                            de, dU, dP, b->d_status + tube);
+                                                            de, dU, dP, b->d_status + tube, nullptr);
     else
       rlb::k_read<M, float><<<grid, block, 0, b->stream>>>(static_cast<const float *>(tube_buf(b, tube, cur)), g, dn,
-                                                           de, dU, dP, b->d_status + tube);
+                                                           de, dU, dP, b->d_status + tube, nullptr);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -1026,10 +1192,10 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
     using M = decltype(m);
     if (r.precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, st>>>(reinterpret_cast<const double *>(curp), g, dn, de, dU, dP,
-                                                     sv->d_status + q->slot);
+                                                     sv->d_status + q->slot, nullptr);
     else
       rlb::k_read<M, float><<<grid, block, 0, st>>>(reinterpret_cast<const float *>(curp), g, dn, de, dU, dP,
-                                                    sv->d_status + q->slot);
+                                                    sv->d_status + q->slot, nullptr);
     return 0;
   });
   hipError_t e = hipGetLastError();

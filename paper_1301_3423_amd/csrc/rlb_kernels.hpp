@@ -161,17 +161,20 @@ inline constexpr int stash_rows = stash_n<M, S> > 0 ? stash_n<M, S> : 1;
 // One lattice update of `cell` by the two lanes (c, c + 32) of a wavefront
 // (see above); `lds` is the block's stash of the last shell (float64 only,
 // [stash_n][block size]).  Cells at or beyond g.cells are computed for a
-// clamped cell and never stored.  OR-s this cell's flags into `flags`.
-template <class M, class S, int TB>
+// clamped cell and never stored; with WALLS, solid cells (solid[cell] != 0)
+// are computed but never stored either.  OR-s this cell's flags into `flags`.
+template <class M, class S, int TB, bool WALLS = false>
 __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__restrict__ nxt, const Geom &g,
-                                               const Relax &rx, int cell, S (*lds)[TB], unsigned &flags) {
+                                               const Relax &rx, int cell, S (*lds)[TB], unsigned &flags,
+                                               const uint8_t *__restrict__ solid = nullptr) {
   constexpr int NPAIR = M::Q / 2;
   constexpr int STASH_BEGIN = stash_begin<M, S>;
   const int lane = threadIdx.x & 63;
   const int m = lane >> 5;
   const int sigma = 1 - 2 * m;
-  const bool active = cell < g.cells;
+  bool active = cell < g.cells;
   if (!active) cell = g.cells - 1; // keeps the partner exchange whole; never stored
+  if constexpr (WALLS) active = active && solid[cell] == 0;
   int x, y, z;
   cell_coords(cell, g, x, y, z);
   S f[NPAIR];
@@ -268,15 +271,16 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
 }
 
 
-template <class M, class S>
+template <class M, class S, bool WALLS>
 __global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
-k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status,
+       const uint8_t *__restrict__ solid) {
   constexpr int TB = pair_block<S>;
   __shared__ S lds[stash_rows<M, S>][TB];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
   unsigned flags = 0;
-  pair_cell_step<M, S, TB>(cur, nxt, g, rx, cell, lds, flags);
+  pair_cell_step<M, S, TB, WALLS>(cur, nxt, g, rx, cell, lds, flags, solid);
   if (flags) atomicOr(status, flags);
 }
 
@@ -375,13 +379,18 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
 // population array, and the lanes only carry the 13 wrapped x offsets.
 // A lane owns a whole cell and uses the inversion pairs directly
 // (s = f_i + f_inv(i) for the even moments, d = f_i - f_inv(i) for the odd
-// ones, and f^eq = w (E +- O) for the two members).
-template <class M, class S>
+// ones, and f^eq = w (E +- O) for the two members).  With WALLS, lanes of
+// solid cells leave at once.
+template <class M, class S, bool WALLS>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status) {
+k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status,
+           const uint8_t *__restrict__ solid) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int cell = blk * BLOCK + threadIdx.x;
   if (cell >= g.cells) return; // whole wavefronts only: cells is a multiple of 64
+  if constexpr (WALLS) {
+    if (solid[cell]) return;
+  }
   const int x = cell % g.nx;
   const int row = __builtin_amdgcn_readfirstlane(cell / g.nx);
   const int y = row % g.ny, z = row / g.ny;
@@ -453,13 +462,23 @@ __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, c
   if (flags) atomicOr(status, flags);
 }
 
-// Macroscopic fields of the current pre-collision state.
+// Macroscopic fields of the current pre-collision state (zero at solid
+// cells when `solid` is given).
 template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom g, double *__restrict__ n_,
                                                 double *__restrict__ eps_, double *__restrict__ U_,
-                                                double *__restrict__ P_, unsigned *__restrict__ status) {
+                                                double *__restrict__ P_, unsigned *__restrict__ status,
+                                                const uint8_t *__restrict__ solid) {
   const int cell = blockIdx.x * BLOCK + threadIdx.x;
   if (cell >= g.cells) return;
+  if (solid && solid[cell]) {
+    if (n_) n_[cell] = 0.0;
+    if (eps_) eps_[cell] = 0.0;
+    if (P_) P_[cell] = 0.0;
+    if (U_)
+      for (int k = 0; k < 4; ++k) U_[k * g.cells + cell] = 0.0;
+    return;
+  }
   int x, y, z;
   cell_coords(cell, g, x, y, z);
   const Shifts sh(x, y, z, g);
@@ -478,6 +497,57 @@ __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom 
     U_[3 * g.cells + cell] = fr.Uz;
   }
   if (flags) atomicOr(status, flags);
+}
+
+// ---- solid walls: link-wise bounce-back ------------------------------------
+//
+// A population i whose source cell s = x - theta_i is solid must arrive at
+// fluid cell x as the post-collision value of the inverse population at x.
+// In the pull storage the next step reads population i of x from slot
+// (i, s), so after each step the slot of the solid cell receives that value:
+// nxt[i][s] = nxt[inv(i)][x] (inv(i) = i ^ 1).  Solid cells are never
+// stored by the step kernels, so these slots are free; the written slots
+// (solid cells) and the read slots (fluid cells) never overlap.
+struct Link {
+  int32_t dst; // solid cell s
+  int32_t src; // fluid cell x = s + theta_pop
+  int32_t pop; // population i
+};
+
+template <class S>
+__global__ void __launch_bounds__(BLOCK) k_bounce(S *__restrict__ nxt, const Link *__restrict__ links,
+                                                  int64_t nlinks, int64_t stride) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (k >= nlinks) return;
+  const Link l = links[k];
+  nxt[l.pop * stride + l.dst] = nxt[(l.pop ^ 1) * stride + l.src];
+}
+
+// Per-cell N^0 and T^{0 nu} of the current state (zero at solid cells):
+// out[k * cells + cell] for k = N^0, T^00, T^0x, T^0y, T^0z.  With walls the
+// per-population totals of k_popsum no longer give the box totals (solid
+// slots hold copies), so the totals are summed per cell instead.
+template <class M, class S>
+__global__ void __launch_bounds__(BLOCK) k_cell_conserved(const S *__restrict__ cur, Geom g,
+                                                          const uint8_t *__restrict__ solid,
+                                                          double *__restrict__ out) {
+  const int cell = blockIdx.x * BLOCK + threadIdx.x;
+  if (cell >= g.cells) return;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!solid[cell]) {
+    int x, y, z;
+    cell_coords(cell, g, x, y, z);
+    const Shifts sh(x, y, z, g);
+    S f[M::Q];
+    gather<M>(cur, g, sh, f);
+    const Moments m = moments<M>(f);
+    v[0] = m.N0;
+    v[1] = m.T00;
+    v[2] = m.T0x;
+    v[3] = m.T0y;
+    v[4] = m.T0z;
+  }
+  for (int k = 0; k < 5; ++k) out[static_cast<int64_t>(k) * g.cells + cell] = v[k];
 }
 
 // Per-population sums over all cells (streaming keeps each of them), in a

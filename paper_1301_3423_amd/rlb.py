@@ -32,7 +32,7 @@ EXPORTS = ("rlb_lattice_info", "rlb_state_bytes", "rlb_create", "rlb_init_fields
            "rlb_batch_bytes", "rlb_batch_create", "rlb_batch_init", "rlb_batch_step", "rlb_batch_read",
            "rlb_batch_status", "rlb_batch_destroy", "rlb_request_bytes", "rlb_server_create",
            "rlb_server_submit", "rlb_server_poll", "rlb_server_pending", "rlb_server_destroy",
-           "rlb_strerror", "rlb_last_error")
+           "rlb_walls_bytes", "rlb_set_walls", "rlb_strerror", "rlb_last_error")
 REQ_TUBE, REQ_BOX = 0, 1
 
 
@@ -123,6 +123,9 @@ def lib():
         L.rlb_server_pending.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.rlb_server_destroy.argtypes = [vp]
         L.rlb_server_destroy.restype = None
+        L.rlb_walls_bytes.argtypes = [i32, i32, i32, i32, vp]
+        L.rlb_walls_bytes.restype = ctypes.c_size_t
+        L.rlb_set_walls.argtypes = [vp, vp, vp, ctypes.c_size_t]
         L.rlb_strerror.argtypes = [ctypes.c_int]
         L.rlb_strerror.restype = ctypes.c_char_p
         L.rlb_last_error.restype = ctypes.c_char_p
@@ -246,6 +249,27 @@ class Solver:
         t = ctypes.c_int64()
         check(lib().rlb_status(self._h, ctypes.byref(fl), ctypes.byref(t)))
         return fl.value, t.value
+
+    def set_walls(self, solid):
+        """Solid cells (array of nz*ny*nx, non-zero = solid; bounce-back
+        walls), or None to remove them.  The device copy lives in a torch
+        buffer owned by this object."""
+        if solid is None:
+            check(lib().rlb_set_walls(self._h, None, None, 0))
+            self._walls = None
+            return
+        mask = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)
+        if mask.size != self.cells:
+            raise ValueError("mask has %d values, expected %d" % (mask.size, self.cells))
+        nz, ny, nx = self.shape
+        nbytes = lib().rlb_walls_bytes(self.order, nx, ny, nz, ctypes.c_void_p(mask.ctypes.data))
+        if nbytes == 0:
+            raise RLBError(EINVAL, "invalid mask (every cell solid?)")
+        import torch
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        check(lib().rlb_set_walls(self._h, ctypes.c_void_p(mask.ctypes.data), ctypes.c_void_p(buf.data_ptr()),
+                                  nbytes))
+        self._walls = buf
 
     def save(self, path):
         check(lib().rlb_save(self._h, str(path).encode()))

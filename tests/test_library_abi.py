@@ -104,3 +104,29 @@ def test_create_rejects_bad_arguments():
     assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
     assert b"order" in L.rlb_last_error()
     assert L.rlb_step(None, 1) == rlb.EINVAL
+
+
+@pytest.mark.parametrize("order", [3, 2])
+def test_walls_bytes_counts_bounce_back_links(order):
+    """rlb_walls_bytes: the mask (rounded to 256 B) plus 12 B per
+    (solid cell, population) pair whose target cell is fluid, counted here
+    independently from the table."""
+    import ctypes
+    from oracle.lattice import model_lattice
+    lat = model_lattice(order)
+    nx, ny, nz = 7, 5, 9
+    rng = np.random.default_rng(order)
+    solid = (rng.uniform(size=(nz, ny, nx)) < 0.3).astype(np.uint8)
+    n = 0
+    for z, y, x in zip(*np.nonzero(solid)):
+        for tx, ty, tz in lat.theta:
+            if not solid[(z + tz) % nz, (y + ty) % ny, (x + tx) % nx]:
+                n += 1
+    def a256(v):
+        return (v + 255) // 256 * 256
+    got = rlb.lib().rlb_walls_bytes(order, nx, ny, nz, ctypes.c_void_p(solid.ctypes.data))
+    assert got == a256(nx * ny * nz) + a256(12 * n)
+    full = np.ones((nz, ny, nx), dtype=np.uint8)
+    assert rlb.lib().rlb_walls_bytes(order, nx, ny, nz, ctypes.c_void_p(full.ctypes.data)) == 0
+    assert rlb.lib().rlb_walls_bytes(order, nx, ny, nz, None) == 0
+    assert rlb.lib().rlb_walls_bytes(5, nx, ny, nz, ctypes.c_void_p(solid.ctypes.data)) == 0
