@@ -29,8 +29,8 @@ Q_OF_ORDER = {3: 128, 2: 66}
 def kernel_name(order, precision, edge):
     """The step kernel the library launches for a box of this edge."""
     if precision == "fp64":
-        return "k_step<Model<%d>, double>" % order
-    return ("k_step_row<Model<%d>, float>" if edge % 64 == 0 else "k_step<Model<%d>, float>") % order
+        return "k_step<Model<%d>, double, false>" % order
+    return ("k_step_row<Model<%d>, float, false>" if edge % 64 == 0 else "k_step<Model<%d>, float, false>") % order
 
 
 def parse():
