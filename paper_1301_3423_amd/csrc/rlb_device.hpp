@@ -282,8 +282,12 @@ struct Frame {
 //   r(v) = (E - M.v) v - (M - S v) = 0,   eps = E - M.v,
 // solved here by Newton's method with Jacobian (E - M.v) I - v M^T + S,
 // started from the exact solution for an ideal fluid with P = eps/3:
-// |v0| = 3x / (2 + sqrt(4 - 3x^2)) along M, x = |M|/E.
-// Then n = U_mu N^mu and T = eps / (3 n).  Returns RLB flags.
+// |v0| = 3x / (2 + sqrt(4 - 3x^2)) along M, x = |M|/E.  It stops when the
+// update is below 1e-12 of |v|, or one iteration earlier once convergence is
+// quadratic: after updates d_prev and d with d <= d_prev / 100, the next
+// update would be about d^3 / d_prev^2, and below 1e-14 |v| it is not taken
+// (from the ideal-fluid start this saves the last of the usual three
+// iterations).  Then n = U_mu N^mu and T = eps / (3 n).  Returns RLB flags.
 __device__ __forceinline__ unsigned landau_frame(const Moments &m, Frame &fr) {
   const double E = m.T00, Mx = m.T0x, My = m.T0y, Mz = m.T0z;
   const double Sxx = m.Txx, Syy = m.Tyy, Szz = m.Tzz, Sxy = m.Txy, Sxz = m.Txz, Syz = m.Tyz;
@@ -294,6 +298,7 @@ __device__ __forceinline__ unsigned landau_frame(const Moments &m, Frame &fr) {
   const double sc = (Mabs > 0.0) ? v0 / Mabs : 0.0;
   double vx = Mx * sc, vy = My * sc, vz = Mz * sc;
   bool converged = false;
+  double dprev = 0.0;
   for (int it = 0; it < 24; ++it) {
     const double a = E - (Mx * vx + My * vy + Mz * vz);
     const double rx = a * vx - Mx + (Sxx * vx + Sxy * vy + Sxz * vz);
@@ -314,10 +319,12 @@ __device__ __forceinline__ unsigned landau_frame(const Moments &m, Frame &fr) {
     vz -= dz;
     const double dmax = __builtin_fmax(__builtin_fabs(dx), __builtin_fmax(__builtin_fabs(dy), __builtin_fabs(dz)));
     const double vmax = __builtin_fmax(__builtin_fabs(vx), __builtin_fmax(__builtin_fabs(vy), __builtin_fabs(vz)));
-    if (dmax <= 1e-12 * vmax || dmax < 1e-300) {
+    const bool settled = it > 0 && dmax <= 0.01 * dprev && dmax * dmax * dmax <= 1e-14 * vmax * dprev * dprev;
+    if (dmax <= 1e-12 * vmax || dmax < 1e-300 || settled) {
       converged = true;
       break;
     }
+    dprev = dmax;
   }
   unsigned flags = converged ? 0u : FLAG_LANDAU;
   const double v2 = vx * vx + vy * vy + vz * vz;
