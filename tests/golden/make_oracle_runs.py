@@ -12,14 +12,20 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-import oracle  # noqa: E402
 from oracle import rlb  # noqa: E402
+from oracle.lattice import model_lattice  # noqa: E402
 from paper_1301_3423_amd import inputs  # noqa: E402
 
-# name: (shape, field recipe, relaxation, checkpoints)
+# name: (shape, field recipe, relaxation, checkpoints, model order, walls)
 RUNS = {
-    "box": ((16, 12, 10), ("box", 0.6, 3), dict(eta_s=0.5), (500, 2000)),
-    "tube": ((1, 1, 400), ("tube", 0.5), dict(eta_s=0.1), (500, 2000)),
+    "box": ((16, 12, 10), ("box", 0.6, 3), dict(eta_s=0.5), (500, 2000), 3, None),
+    "tube": ((1, 1, 400), ("tube", 0.5), dict(eta_s=0.1), (500, 2000), 3, None),
+    "box_order2": ((16, 12, 10), ("box", 0.6, 3), dict(eta_s=0.5), (500, 2000), 2, None),
+    "tube_order2": ((1, 1, 400), ("tube", 0.5), dict(eta_s=0.1), (500, 2000), 2, None),
+    # a channel: solid slabs of 6 cells at both y ends, flow along x
+    "channel": ((8, 24, 6), ("box", 0.3, 4), dict(eta_s=0.2), (250, 1000), 3, ("slabs", 1, 6)),
+    # a closed shock tube: solid slabs of 6 cells at both z ends
+    "closed_tube": ((1, 1, 300), ("tube", 0.5), dict(eta_s=0.1), (250, 1000), 3, ("slabs", 0, 6)),
 }
 
 
@@ -29,11 +35,27 @@ def fields_of(shape, recipe):
     return inputs.shock_tube(shape[2], 1.0, recipe[1])
 
 
+def solid_of(shape, walls):
+    """Solid mask [nz, ny, nx] of a wall recipe (None: no walls); axis 0 is z,
+    1 is y of the mask array."""
+    if walls is None:
+        return None
+    nx, ny, nz = shape
+    kind, axis, thick = walls
+    assert kind == "slabs"
+    m = np.zeros((nz, ny, nx), dtype=bool)
+    idx = [slice(None)] * 3
+    idx[axis] = slice(0, thick)
+    m[tuple(idx)] = True
+    idx[axis] = slice(m.shape[axis] - thick, m.shape[axis])
+    m[tuple(idx)] = True
+    return m
+
+
 def main():
-    lat = oracle.load_lattice()
     out = {}
-    for name, (shape, recipe, relax, checkpoints) in RUNS.items():
-        s = rlb.Solver(*shape, lat=lat, **relax)
+    for name, (shape, recipe, relax, checkpoints, order, walls) in RUNS.items():
+        s = rlb.Solver(*shape, lat=model_lattice(order), order=order, solid=solid_of(shape, walls), **relax)
         s.init_fields(*fields_of(shape, recipe))
         for cp in checkpoints:
             s.step(cp - s.t)
