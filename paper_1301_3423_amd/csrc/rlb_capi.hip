@@ -116,7 +116,7 @@ template <class M, bool WALLS>
 void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r) {
   const uint8_t *solid = WALLS ? s->d_solid : nullptr;
   if (s->cfg.precision == RLB_FP64) {
-    constexpr int TB = rlb::pair_block<double>;
+    constexpr int TB = rlb::pair_block<M, double>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     rlb::k_step<M, double, WALLS><<<grid, block, 0, s->stream>>>(
         static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r, s->status, solid);
@@ -125,7 +125,7 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
     rlb::k_step_row<M, float, WALLS><<<grid, block, 0, s->stream>>>(
         static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);
   } else {
-    constexpr int TB = rlb::pair_block<float>;
+    constexpr int TB = rlb::pair_block<M, float>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     rlb::k_step<M, float, WALLS><<<grid, block, 0, s->stream>>>(
         static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);

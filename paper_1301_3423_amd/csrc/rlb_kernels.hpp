@@ -93,11 +93,12 @@ __device__ __forceinline__ void relax_cell(const S (&f)[M::Q], const Frame &fr, 
 // odd moments, the odd equilibrium coefficients and the velocity.  The 14
 // moments are summed across the two lanes (identical results in both), and
 // both lanes solve the same Landau problem.
-// block sizes of the two-lane step kernels (128 cells per block)
-inline constexpr int BLOCK_PAIR64 = 256;
-inline constexpr int BLOCK_PAIR32 = 256;
-template <class S>
-inline constexpr int pair_block = sizeof(S) == 8 ? BLOCK_PAIR64 : BLOCK_PAIR32;
+// Block sizes of the two-lane step kernels: 512 threads (256 cells) for the
+// third-order float64 kernel, whose LDS stash then fills 128 KB of the CU
+// (measured 1-2 % faster than 256 threads at 256^3), 256 threads (128
+// cells) otherwise.
+template <class M, class S>
+inline constexpr int pair_block = (sizeof(S) == 8 && M::Q == 128) ? 512 : 256;
 
 // (c - s) mod n for a shift s known only at run time, |s| <= MAXD.
 __device__ __forceinline__ int wrap_rt(int c, int s, int n) {
@@ -139,9 +140,9 @@ __device__ __forceinline__ double add_partner(double v) { return v + __shfl_xor(
 // reads whole source rows, so it shares no cache line with other blocks.
 
 // Float64 populations of the last stash_n pairs of the third-order model
-// wait in LDS between the moment sums and the relaxation (64 KB per
-// 256-thread block), which keeps the live registers of the float64 kernels
-// within two waves per SIMD.  The 33 pairs of the second-order model fit
+// wait in LDS between the moment sums and the relaxation (256 B per thread,
+// 128 KB per 512-thread block), which keeps the live registers of the
+// float64 kernels within two waves per SIMD.  The 33 pairs of the second-order model fit
 // in registers.
 template <class M, class S>
 inline constexpr int stash_n = (sizeof(S) == 8 && M::Q == 128) ? 32 : 0;
@@ -279,10 +280,10 @@ __device__ __forceinline__ int pair_block_order(int b, int nb) {
 }
 
 template <class M, class S, bool WALLS>
-__global__ void __launch_bounds__(pair_block<S>) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((pair_block<M, S>)) __attribute__((amdgpu_waves_per_eu(2)))
 k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status,
        const uint8_t *__restrict__ solid) {
-  constexpr int TB = pair_block<S>;
+  constexpr int TB = pair_block<M, S>;
   __shared__ S lds[stash_rows<M, S>][TB];
   const int blk = pair_block_order(blockIdx.x, gridDim.x);
   const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
