@@ -69,3 +69,34 @@ def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed, ord
         worst = max(worst, max(errs))
         assert max(errs) <= tol, (c, errs)
     note("worst sampled relative error %.2e" % worst)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("order", [3, 2])
+def test_shear_wave_decays_at_the_kinetic_viscosity(precision, order):
+    """A property that holds at any size: a small shear wave v_x = A sin(kz)
+    decays at nu = (tau - 1/2) R^2 / 5 cells^2/step (the Anderson-Witting
+    viscosity, pinned on the oracle in test_oracle_viscosity.py), here on a
+    64 x 4 x 128 box through the kernels bench.py times (the row kernel for
+    mixed precision)."""
+    nx, ny, nz, tau = 64, 4, 128, 0.8
+    z = np.arange(nz)
+    mode = np.sin(2 * np.pi * z / nz)
+    C = nx * ny * nz
+    vx = np.broadcast_to((1e-3 * mode)[:, None, None], (nz, ny, nx)).ravel()
+    s = rlb.Solver(nx, ny, nz, precision=precision, tau=tau, order=order)
+    s.init_fields(np.ones(C), np.full(C, 3.0), vx, np.zeros(C), np.zeros(C))
+    t, a = [], []
+    for _ in range(10):
+        s.step(5)
+        r = s.read_fields()
+        v = (r["U"][1] / r["U"][0]).reshape(nz, ny, nx).mean(axis=(1, 2))
+        t.append(s.status()[1])
+        a.append(np.dot(v, mode) * 2 / nz)
+    t, a = np.array(t), np.array(a)
+    sel = t >= 20
+    rate = -np.polyfit(t[sel], np.log(np.abs(a[sel])), 1)[0]
+    R = {3: np.sqrt(41.0), 2: 3.0}[order]
+    ratio = rate / (2 * np.pi / nz) ** 2 / ((tau - 0.5) * R * R / 5)
+    note("order %d %s: nu / nu_AW = %.4f" % (order, precision, ratio))
+    assert abs(ratio - 1) < 0.02, ratio
