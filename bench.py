@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-tubes", action="store_true")
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--no-aa", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
@@ -127,9 +128,9 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def run_box(edge, precision, fields, steps, warmup, eta_s, order=3, solid=None):
+def run_box(edge, precision, fields, steps, warmup, eta_s, order=3, solid=None, pattern="ab"):
     from paper_1301_3423_amd import rlb
-    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order)
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order, pattern=pattern)
     if solid is not None:
         s.set_walls(solid)
     s.init_fields(*fields)
@@ -365,6 +366,18 @@ def main():
                  "fluid_mlups": round(r["mlups"] * fluid / edge ** 3, 2), "ms_per_step": round(r["ms_per_step"], 4),
                  "vs_periodic": round(r["ms_per_step"] / mixed["ms_per_step"], 3),
                  "status_flags": r["flags"], "N0_drift": r["conservation_drift_N0"]}
+    aa = {}
+    if not args.no_aa:
+        for prec, ab in (("mixed", mixed), ("fp64", fp64)):
+            if ab is None:
+                continue
+            r = run_box(edge, prec, fields, args.steps, args.warmup, args.eta_s, pattern="aa")
+            print("bench: AA %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
+            same = all(np.array_equal(r["fields"][k], ab["fields"][k]) for k in ("n", "eps", "P", "U"))
+            aa[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
+                        "vs_ab": round(ab["ms_per_step"] / r["ms_per_step"], 3),
+                        "achieved_GBps": round(r["achieved_gbs"], 1), "fields_equal_ab": bool(same),
+                        "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
     tubes = {}
     if not args.no_tubes:
         for prec in ("fp64", "mixed"):
@@ -421,6 +434,9 @@ def main():
                                             "Appendix A (66 points, R = 3)" % edge, **second}
     if walls is not None:
         line["walls"] = walls
+    if aa:
+        line["aa_pattern"] = {"workload": "the same %d^3 box, fields and steps, third order, one population "
+                                          "buffer updated in place (AA pattern) instead of two" % edge, **aa}
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

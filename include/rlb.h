@@ -68,6 +68,18 @@ extern "C" {
 #define RLB_ORDER3 3 /* third-order model: 128 points, R^2 = 41, 4 shells */
 #define RLB_ORDER2 2 /* second-order model: 66 points, R^2 = 9, 3 shells  */
 
+/* ---- streaming pattern ----------------------------------------------------
+ * RLB_PATTERN_AB: two population buffers; each step reads one and writes the
+ * other (pull streaming).  RLB_PATTERN_AA: one buffer updated in place, the
+ * "AA" pattern: even steps read and write each cell's own slots (storing
+ * population i in the slot of its inverse), odd steps read the inverse slots
+ * of the neighbours x - theta_i and write to x + theta_i, which restores the
+ * natural layout.  Same arithmetic and results, half the population memory
+ * (plus 56 bytes per cell of staging), so larger boxes fit: about 512^3 in
+ * float64 with the third-order model on 288 GB.  Walls need AB. */
+#define RLB_PATTERN_AB 0
+#define RLB_PATTERN_AA 1
+
 /* ---- relaxation time ---------------------------------------------------- */
 #define RLB_TAU_FIXED 0 /* tau is a constant (> 1/2)                         */
 #define RLB_TAU_ETA_S 1 /* tau per cell and step from eta/s:
@@ -119,15 +131,16 @@ typedef struct rlb_config {
   double tau;         /* relaxation time when tau_mode == RLB_TAU_FIXED   */
   double eta_s;       /* eta/s (> 0) when tau_mode == RLB_TAU_ETA_S        */
   int32_t order;      /* model: 0 or RLB_ORDER3, or RLB_ORDER2             */
+  int32_t pattern;    /* RLB_PATTERN_AB (0) or RLB_PATTERN_AA              */
 } rlb_config;
 
 typedef struct rlb_solver rlb_solver;
 
-/* Bytes of device memory a box of this size and model needs: two
- * population buffers (the kernels read one and write the other) plus a
- * 4 KiB status area.  Returns 0 for invalid sizes, precision or order.
- * Pure function. */
-size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order);
+/* Bytes of device memory a box of this size, model and pattern needs: two
+ * population buffers (AB) or one buffer and a staging area of 7 doubles per
+ * cell (AA), plus a 4 KiB status area.  Returns 0 for invalid sizes,
+ * precision, order or pattern.  Pure function. */
+size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order, int32_t pattern);
 
 /* Creates a solver over caller-owned device memory d_buf of `bytes` bytes
  * (>= rlb_state_bytes, 256-byte aligned) on `stream` of the current device.

@@ -38,6 +38,10 @@ size_t elem_bytes(int precision) { return precision == RLB_MIXED ? 4 : 8; }
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Device staging of an AA solver (it has no idle buffer): 7 doubles per
+// cell for host fields, which also holds the partial sums of rlb_conserved.
+size_t aa_stage_bytes(int64_t cells) { return align256(static_cast<size_t>(cells) * 7 * sizeof(double)); }
+
 // Elements between consecutive population arrays: the cell count rounded up
 // to 256 bytes, plus 256 bytes, so that the arrays do not all start at the
 // same offset modulo a large power of two.
@@ -82,6 +86,7 @@ struct rlb_solver {
   int cur;
   int64_t t;
   bool initialized;
+  double *stage; // device staging for host fields and sums: the idle buffer (AB) or its own area (AA)
   // solid walls (rlb_set_walls): mask and bounce-back links in caller memory
   const uint8_t *d_solid = nullptr;
   const rlb::Link *d_links = nullptr;
@@ -111,24 +116,34 @@ rlb::Relax relax_of(const rlb_solver *s) {
 
 unsigned grid_of(int64_t cells) { return static_cast<unsigned>((cells + rlb::BLOCK - 1) / rlb::BLOCK); }
 
-// The step kernels of one box, with or without walls.
-template <class M, bool WALLS>
+// Layout of the current state: PULL storage (two buffers), or the natural
+// (even t) or swapped (odd t) state of the single AA buffer.
+int access_of(const rlb_solver *s) {
+  if (s->cfg.pattern != RLB_PATTERN_AA) return rlb::PULL;
+  return (s->t & 1) ? rlb::AA_ODD : rlb::AA_EVEN;
+}
+
+// The step kernels of one box, with or without walls, for access AC (with
+// AA the input and output buffer is the same).
+template <class M, bool WALLS, int AC>
 void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r) {
   const uint8_t *solid = WALLS ? s->d_solid : nullptr;
+  void *in = s->buf[s->cur];
+  void *out = AC == rlb::PULL ? s->buf[1 - s->cur] : s->buf[s->cur];
   if (s->cfg.precision == RLB_FP64) {
     constexpr int TB = rlb::pair_block<M, double>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-    rlb::k_step<M, double, WALLS><<<grid, block, 0, s->stream>>>(
-        static_cast<const double *>(s->buf[s->cur]), static_cast<double *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+    rlb::k_step<M, double, WALLS, AC><<<grid, block, 0, s->stream>>>(
+        static_cast<const double *>(in), static_cast<double *>(out), g, r, s->status, solid);
   } else if (s->cfg.nx % 64 == 0) {
     const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
-    rlb::k_step_row<M, float, WALLS><<<grid, block, 0, s->stream>>>(
-        static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+    rlb::k_step_row<M, float, WALLS, AC><<<grid, block, 0, s->stream>>>(
+        static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
   } else {
     constexpr int TB = rlb::pair_block<M, float>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
-    rlb::k_step<M, float, WALLS><<<grid, block, 0, s->stream>>>(
-        static_cast<const float *>(s->buf[s->cur]), static_cast<float *>(s->buf[1 - s->cur]), g, r, s->status, solid);
+    rlb::k_step<M, float, WALLS, AC><<<grid, block, 0, s->stream>>>(
+        static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
   }
   if constexpr (WALLS) {
     if (s->nlinks > 0) {
@@ -145,24 +160,35 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
 
 // float64: the two-lane kernel; float32: one lane per cell when rows are
 // whole wavefronts (nx % 64 == 0), else the two-lane kernel; with walls, the
-// bounce-back copies follow on the same stream.
+// bounce-back copies follow on the same stream.  The AA pattern alternates
+// its even and odd steps in one buffer.
 int launch_step(rlb_solver *s) {
   const rlb::Geom g = geom_of(s);
   const rlb::Relax r = relax_of(s);
+  const int ac = access_of(s);
   with_model(s->cfg.order, [&](auto m) {
     using M = decltype(m);
     if (s->d_solid)
-      launch_step_kernels<M, true>(s, g, r);
+      launch_step_kernels<M, true, rlb::PULL>(s, g, r);
+    else if (ac == rlb::AA_EVEN)
+      launch_step_kernels<M, false, rlb::AA_EVEN>(s, g, r);
+    else if (ac == rlb::AA_ODD)
+      launch_step_kernels<M, false, rlb::AA_ODD>(s, g, r);
     else
-      launch_step_kernels<M, false>(s, g, r);
+      launch_step_kernels<M, false, rlb::PULL>(s, g, r);
     return 0;
   });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_step launch");
-  s->cur = 1 - s->cur;
+  if (ac == rlb::PULL) s->cur = 1 - s->cur;
   s->t += 1;
   return RLB_OK;
 }
+
+// Device staging for host fields and sums: the AA solver's own area, or the
+// idle population buffer of an AB solver (large enough: 7 doubles per cell
+// fit in 66 values of either precision).
+double *staging(rlb_solver *s) { return s->stage ? s->stage : static_cast<double *>(s->buf[1 - s->cur]); }
 
 bool finite_all(const double *a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
@@ -220,12 +246,14 @@ int rlb_lattice_info(int32_t order, rlb_lattice_t *out) {
   });
 }
 
-size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order) {
+size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, int32_t order, int32_t pattern) {
   if (!valid_dims(nx, ny, nz) || (precision != RLB_FP64 && precision != RLB_MIXED) || !valid_order(order)) return 0;
+  if (pattern != RLB_PATTERN_AB && pattern != RLB_PATTERN_AA) return 0;
   const int64_t cells = static_cast<int64_t>(nx) * ny * nz;
   const size_t buf =
       static_cast<size_t>(q_of(norm_order(order))) * pop_stride(cells, precision) * elem_bytes(precision);
-  return 2 * buf + STATUS_BYTES;
+  if (pattern == RLB_PATTERN_AB) return 2 * buf + STATUS_BYTES;
+  return buf + STATUS_BYTES + aa_stage_bytes(cells);
 }
 
 int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t bytes, void *stream) {
@@ -235,6 +263,8 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
   if (cfg->precision != RLB_FP64 && cfg->precision != RLB_MIXED)
     return fail(RLB_EINVAL, "rlb_create: bad precision");
   if (!valid_order(cfg->order)) return fail(RLB_EINVAL, "rlb_create: order must be 0, 2 or 3");
+  if (cfg->pattern != RLB_PATTERN_AB && cfg->pattern != RLB_PATTERN_AA)
+    return fail(RLB_EINVAL, "rlb_create: pattern must be RLB_PATTERN_AB or RLB_PATTERN_AA");
   if (cfg->tau_mode == RLB_TAU_FIXED) {
     if (!(cfg->tau > 0.5) || !std::isfinite(cfg->tau)) return fail(RLB_EINVAL, "rlb_create: tau must exceed 1/2");
   } else if (cfg->tau_mode == RLB_TAU_ETA_S) {
@@ -243,7 +273,7 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
     return fail(RLB_EINVAL, "rlb_create: bad tau_mode");
   }
   if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_create: buffer not 256-byte aligned");
-  const size_t need = rlb_state_bytes(cfg->nx, cfg->ny, cfg->nz, cfg->precision, cfg->order);
+  const size_t need = rlb_state_bytes(cfg->nx, cfg->ny, cfg->nz, cfg->precision, cfg->order, cfg->pattern);
   if (bytes < need)
     return fail(RLB_ENOMEM, "rlb_create: buffer has " + std::to_string(bytes) + " bytes, needs " + std::to_string(need));
   int dev = 0;
@@ -260,8 +290,15 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
   s->stride = pop_stride(s->cells, cfg->precision);
   s->buf_bytes = static_cast<size_t>(q_of(s->cfg.order)) * s->stride * elem_bytes(cfg->precision);
   s->buf[0] = s->base;
-  s->buf[1] = s->base + s->buf_bytes;
-  s->status = reinterpret_cast<unsigned *>(s->base + 2 * s->buf_bytes);
+  if (cfg->pattern == RLB_PATTERN_AA) {
+    s->buf[1] = s->base; // one buffer
+    s->status = reinterpret_cast<unsigned *>(s->base + s->buf_bytes);
+    s->stage = reinterpret_cast<double *>(s->base + s->buf_bytes + STATUS_BYTES);
+  } else {
+    s->buf[1] = s->base + s->buf_bytes;
+    s->status = reinterpret_cast<unsigned *>(s->base + 2 * s->buf_bytes);
+    s->stage = nullptr; // the idle buffer, chosen per call
+  }
   s->cur = 0;
   s->t = 0;
   s->initialized = false;
@@ -274,9 +311,7 @@ int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const dou
   if (!s || !n || !eps || !vx || !vy || !vz) return fail(RLB_EINVAL, "rlb_init_fields: NULL argument");
   const int64_t C = s->cells;
   const double *dn = n, *de = eps, *dx = vx, *dy = vy, *dz = vz;
-  // the idle buffer doubles as staging for host input (5 C doubles fit in
-  // 66 C values of either precision)
-  double *stage = static_cast<double *>(s->buf[1 - s->cur]);
+  double *stage = staging(s);
   if (!on_device) {
     const double *arrs[5] = {n, eps, vx, vy, vz};
     for (auto a : arrs)
@@ -297,14 +332,15 @@ int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const dou
   RLB_HIP(hipMemsetAsync(s->status, 0, sizeof(unsigned), s->stream));
   const rlb::Geom g = geom_of(s);
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
+  const int aa = s->cfg.pattern == RLB_PATTERN_AA ? 1 : 0; // t = 0: the natural AA state
   with_model(s->cfg.order, [&](auto m) {
     using M = decltype(m);
     if (s->cfg.precision == RLB_FP64)
       rlb::k_init<M, double><<<grid, block, 0, s->stream>>>(dn, de, dx, dy, dz, static_cast<double *>(s->buf[s->cur]),
-                                                            g, s->status);
+                                                            g, s->status, aa);
     else
       rlb::k_init<M, float><<<grid, block, 0, s->stream>>>(dn, de, dx, dy, dz, static_cast<float *>(s->buf[s->cur]),
-                                                           g, s->status);
+                                                           g, s->status, aa);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -331,7 +367,7 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
   if (!s->initialized) return fail(RLB_ESTATE, "rlb_read_fields: call rlb_init_fields first");
   const int64_t C = s->cells;
   double *dn = n, *de = eps, *dU = U4, *dP = P;
-  double *stage = static_cast<double *>(s->buf[1 - s->cur]); // 7 C doubles
+  double *stage = staging(s); // 7 C doubles
   if (!on_device) {
     dn = n ? stage : nullptr;
     de = eps ? stage + C : nullptr;
@@ -344,10 +380,10 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
     using M = decltype(m);
     if (s->cfg.precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, s->stream>>>(static_cast<const double *>(s->buf[s->cur]), g, dn, de, dU,
-                                                            dP, s->status, s->d_solid);
+                                                            dP, s->status, s->d_solid, access_of(s));
     else
       rlb::k_read<M, float><<<grid, block, 0, s->stream>>>(static_cast<const float *>(s->buf[s->cur]), g, dn, de, dU,
-                                                           dP, s->status, s->d_solid);
+                                                           dP, s->status, s->d_solid, access_of(s));
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -368,7 +404,7 @@ namespace {
 int conserved_walls(rlb_solver *s, double out[5]) {
   const rlb::Geom g = geom_of(s);
   const int64_t C = s->cells;
-  double *cellv = static_cast<double *>(s->buf[1 - s->cur]); // 5 C doubles
+  double *cellv = staging(s); // 5 C doubles
   const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
   const int nblocks = static_cast<int>((C + chunk - 1) / chunk);
   double *partial = cellv + 5 * C;
@@ -404,7 +440,7 @@ int rlb_conserved(rlb_solver *s, double out[5]) {
   const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
   const int nblocks = static_cast<int>((s->cells + chunk - 1) / chunk);
   const int Q = q_of(s->cfg.order);
-  double *partial = static_cast<double *>(s->buf[1 - s->cur]);
+  double *partial = staging(s);
   double *total = partial + static_cast<size_t>(Q) * nblocks;
   const dim3 grid1(nblocks, Q), block(rlb::BLOCK);
   if (s->cfg.precision == RLB_FP64)
@@ -420,13 +456,15 @@ int rlb_conserved(rlb_solver *s, double out[5]) {
   RLB_HIP(hipMemcpyAsync(tot, total, Q * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
   for (int k = 0; k < 5; ++k) out[k] = 0.0;
+  // in the swapped AA state the values of population i sit in array inv(i)
+  const int swap = access_of(s) == rlb::AA_ODD ? 1 : 0;
   with_model(s->cfg.order, [&](auto m) {
     using M = decltype(m);
     for (int i = 0; i < M::Q; ++i) {
       const rlb::Point &p = M::P[i];
       const double pm[4] = {p.p0, p.p0 * p.tx * M::INV_R, p.p0 * p.ty * M::INV_R, p.p0 * p.tz * M::INV_R};
-      out[0] += p.p0 * tot[i];
-      for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i];
+      out[0] += p.p0 * tot[i ^ swap];
+      for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i ^ swap];
     }
     return 0;
   });
@@ -507,6 +545,7 @@ int rlb_load(rlb_solver *s, const char *path) {
       std::memcmp(h.sha256, lat.sha256, 64) != 0 || h.cfg.nx != s->cfg.nx || h.cfg.ny != s->cfg.ny ||
       h.cfg.nz != s->cfg.nz || h.cfg.precision != s->cfg.precision || h.cfg.tau_mode != s->cfg.tau_mode ||
       h.cfg.tau != s->cfg.tau || h.cfg.eta_s != s->cfg.eta_s || h.cfg.order != s->cfg.order ||
+      h.cfg.pattern != s->cfg.pattern ||
       h.solid_hash != s->solid_hash) {
     std::fclose(fp);
     return fail(RLB_EINVAL, "rlb_load: checkpoint does not match this solver");
@@ -596,6 +635,8 @@ int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes
     s->solid_hash = 0;
     return RLB_OK;
   }
+  if (s->cfg.pattern == RLB_PATTERN_AA)
+    return fail(RLB_EINVAL, "rlb_set_walls: walls need the AB pattern (two buffers)");
   if (!d_buf) return fail(RLB_EINVAL, "rlb_set_walls: NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_buf) % 256 != 0) return fail(RLB_EINVAL, "rlb_set_walls: buffer not 256-byte aligned");
   std::vector<rlb::Link> links;
@@ -814,11 +855,11 @@ int rlb_batch_init(rlb_batch *b, int32_t tube, const double *n, const double *ep
     if (b->precision == RLB_FP64)
       rlb::k_init<M, double><<<grid, block, 0, b->stream>>>(dn, de, dx, dy, dz,
                                                             static_cast<double *>(tube_buf(b, tube, cur)), g,
-                                                            b->d_status + tube);
+                                                            b->d_status + tube, 0);
     else
       rlb::k_init<M, float><<<grid, block, 0, b->stream>>>(dn, de, dx, dy, dz,
                                                            static_cast<float *>(tube_buf(b, tube, cur)), g,
-                                                           b->d_status + tube);
+                                                           b->d_status + tube, 0);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -899,10 +940,10 @@ int rlb_batch_read(rlb_batch *b, int32_t tube, double *n, double *eps, double *U
     using M = decltype(m);
     if (b->precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, b->stream>>>(static_cast<const double *>(tube_buf(b, tube, cur)), g, dn,
-                                                            de, dU, dP, b->d_status + tube, nullptr);
+                                                            de, dU, dP, b->d_status + tube, nullptr, rlb::PULL);
     else
       rlb::k_read<M, float><<<grid, block, 0, b->stream>>>(static_cast<const float *>(tube_buf(b, tube, cur)), g, dn,
-                                                           de, dU, dP, b->d_status + tube, nullptr);
+                                                           de, dU, dP, b->d_status + tube, nullptr, rlb::PULL);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -1087,7 +1128,7 @@ size_t tube_pair_bytes(const rlb_request &r) { return 2 * tube_buffer_bytes(r.nz
 
 size_t request_bytes_of(const rlb_request &r) {
   if (r.kind == RLB_REQ_TUBE) return tube_pair_bytes(r);
-  return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision, r.order));
+  return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision, r.order, RLB_PATTERN_AB));
 }
 
 void finish(rlb_server *sv, ServeReq *q, int rc, unsigned flags) {
@@ -1124,7 +1165,7 @@ int admit(rlb_server *sv, ServeReq *q) {
   q->remaining = r.steps;
   if (r.kind == RLB_REQ_BOX) {
     q->stream_idx = SERVE_TUBE_STREAMS + (sv->next_box_stream++ % SERVE_BOX_STREAMS);
-    rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s, r.order};
+    rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s, r.order, RLB_PATTERN_AB};
     int rc = rlb_create(&q->box, &cfg, sv->pool + q->off, q->bytes, sv->streams[q->stream_idx]);
     if (rc != RLB_OK) return rc;
     return rlb_init_fields(q->box, f, f + C, f + 2 * C, f + 3 * C, f + 4 * C, 0);
@@ -1153,11 +1194,11 @@ int admit(rlb_server *sv, ServeReq *q) {
     if (r.precision == RLB_FP64)
       rlb::k_init<M, double><<<grid, block, 0, st>>>(stage, stage + C, stage + 2 * C, stage + 3 * C, stage + 4 * C,
                                                      reinterpret_cast<double *>(sv->pool + q->off), g,
-                                                     sv->d_status + q->slot);
+                                                     sv->d_status + q->slot, 0);
     else
       rlb::k_init<M, float><<<grid, block, 0, st>>>(stage, stage + C, stage + 2 * C, stage + 3 * C, stage + 4 * C,
                                                     reinterpret_cast<float *>(sv->pool + q->off), g,
-                                                    sv->d_status + q->slot);
+                                                    sv->d_status + q->slot, 0);
     return 0;
   });
   hipError_t e = hipGetLastError();
@@ -1192,10 +1233,10 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
     using M = decltype(m);
     if (r.precision == RLB_FP64)
       rlb::k_read<M, double><<<grid, block, 0, st>>>(reinterpret_cast<const double *>(curp), g, dn, de, dU, dP,
-                                                     sv->d_status + q->slot, nullptr);
+                                                     sv->d_status + q->slot, nullptr, rlb::PULL);
     else
       rlb::k_read<M, float><<<grid, block, 0, st>>>(reinterpret_cast<const float *>(curp), g, dn, de, dU, dP,
-                                                    sv->d_status + q->slot, nullptr);
+                                                    sv->d_status + q->slot, nullptr, rlb::PULL);
     return 0;
   });
   hipError_t e = hipGetLastError();

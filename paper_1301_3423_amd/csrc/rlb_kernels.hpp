@@ -16,6 +16,25 @@ namespace rlb {
 
 inline constexpr int BLOCK = 256;
 
+// How a step reads and writes its populations (slot (i, x) = element
+// i * stride + x of a buffer):
+//   PULL     two buffers: gather cur[i][x - theta_i], store nxt[i][x];
+//   AA_EVEN  one buffer in its natural state, slot (i, x) = f_i(x): read
+//            slot (i, x), store the post-collision f_i to slot (inv(i), x);
+//   AA_ODD   one buffer in the swapped state, slot (inv(i), x - theta_i) =
+//            f_i(x): read those slots and store the post-collision f_i to
+//            slot (i, x + theta_i), which is the natural state again.
+// An AA step writes exactly the slots its own cell read, so the update is
+// in place (the "AA" streaming pattern): one buffer instead of two.
+enum Access { PULL = 0, AA_EVEN = 1, AA_ODD = 2 };
+
+// Population pointers of a step: restrict-qualified for the two-buffer
+// pull, plain for the in-place AA steps (there cur == nxt).
+template <class S, int AC>
+using InPtr = std::conditional_t<AC == PULL, const S *__restrict__, const S *>;
+template <class S, int AC>
+using OutPtr = std::conditional_t<AC == PULL, S *__restrict__, S *>;
+
 template <class S>
 __device__ __forceinline__ S load_at(const S *base, int cell) {
   const uint32_t boff = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
@@ -38,14 +57,20 @@ __device__ __forceinline__ void cell_coords(int cell, const Geom &g, int &x, int
   z = yz / g.ny;
 }
 
-// Gather f_i(x, t) for all points of the model (pull streaming).
+// Gather f_i(x, t) for all points of the model from a buffer laid out for
+// `mode` (an Access value: PULL storage, or the natural or swapped AA state).
 template <class M, class S>
 __device__ __forceinline__ void gather(const S *__restrict__ cur, const Geom &g, const Shifts &sh,
-                                       S (&f)[M::Q]) {
+                                       S (&f)[M::Q], int mode = PULL, int cell = 0) {
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Point P = M::P[i];
-    f[i] = load_at(cur + i * g.stride, sh.back<P.tx, P.ty, P.tz>());
+    if (mode == AA_EVEN)
+      f[i] = load_at(cur + i * g.stride, cell);
+    else if (mode == AA_ODD)
+      f[i] = load_at(cur + (i ^ 1) * g.stride, sh.back<P.tx, P.ty, P.tz>());
+    else
+      f[i] = load_at(cur + i * g.stride, sh.back<P.tx, P.ty, P.tz>());
   });
 }
 
@@ -157,8 +182,9 @@ inline constexpr int stash_rows = stash_n<M, S> > 0 ? stash_n<M, S> : 1;
 // [stash_n][block size]).  Cells at or beyond g.cells are computed for a
 // clamped cell and never stored; with WALLS, solid cells (solid[cell] != 0)
 // are computed but never stored either.  OR-s this cell's flags into `flags`.
-template <class M, class S, int TB, bool WALLS = false>
-__device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__restrict__ nxt, const Geom &g,
+// AC selects the access (PULL, AA_EVEN, AA_ODD); for AA, cur == nxt.
+template <class M, class S, int TB, bool WALLS = false, int AC = PULL>
+__device__ __forceinline__ void pair_cell_step(InPtr<S, AC> cur, OutPtr<S, AC> nxt, const Geom &g,
                                                const Relax &rx, int cell, S (*lds)[TB], unsigned &flags,
                                                const uint8_t *__restrict__ solid = nullptr) {
   constexpr int NPAIR = M::Q / 2;
@@ -172,8 +198,16 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
   int x, y, z;
   cell_coords(cell, g, x, y, z);
   S f[NPAIR];
-  {
-    const HalfShifts sh(x, y, z, sigma, m, g);
+  if constexpr (AC == AA_EVEN) {
+    // own slot (2k + m, x)
+    const int own = m * static_cast<int>(g.stride) + cell;
+    static_for<0, NPAIR>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      f[k] = load_at(cur + (2 * k) * g.stride, own);
+    });
+  } else {
+    // PULL: slot (2k + m, x - sigma theta); AA_ODD: slot (2k + 1 - m, x - sigma theta)
+    const HalfShifts sh(x, y, z, sigma, AC == AA_ODD ? 1 - m : m, g);
     static_for<0, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
       constexpr Point P = M::P[2 * k];
@@ -238,7 +272,15 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
   const CT gg = CT(gdt);
   const double gs = gdt * M::INV_R * sg;
   const CT bx = CT(gs * fr.vx), by = CT(gs * fr.vy), bz = CT(gs * fr.vz);
-  const int out_off = m * static_cast<int>(g.stride) + cell; // same for every point of this lane
+  // AA_ODD stores go to x + sigma theta: the offsets of x - (-sigma) theta
+  struct NoShifts {
+    __device__ NoShifts(int, int, int, int, int, const Geom &) {}
+  };
+  using Fwd = std::conditional_t<AC == AA_ODD, HalfShifts, NoShifts>;
+  const Fwd fwd(x, y, z, -sigma, m, g);
+  // PULL: slot (2k + m, x); AA_EVEN: slot (2k + 1 - m, x); AA_ODD: slot
+  // (2k + m, x + sigma theta), whose offsets depend on the point
+  const int out_off = (AC == AA_EVEN ? 1 - m : m) * static_cast<int>(g.stride) + cell;
   static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
     const ShellCoef<M, CT> s = shell_coefficients<M, l, CT>(e);
@@ -258,7 +300,11 @@ __device__ __forceinline__ void pair_cell_step(const S *__restrict__ cur, S *__r
       else
         a = f[k];
       const CT fs = fmadd(gg - t, feq - a, a);
-      if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
+      if constexpr (AC == AA_ODD) {
+        if (active) store_at(nxt + (2 * k) * g.stride, fwd.template back<P.tx, P.ty, P.tz>(), S(fs));
+      } else {
+        if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
+      }
     });
   });
   if (active) flags |= fl;
@@ -279,16 +325,16 @@ __device__ __forceinline__ int pair_block_order(int b, int nb) {
   return 2 * (xcd + 8 * (slot >> 1)) + (slot & 1);
 }
 
-template <class M, class S, bool WALLS>
+template <class M, class S, bool WALLS, int AC = PULL>
 __global__ void __launch_bounds__((pair_block<M, S>)) __attribute__((amdgpu_waves_per_eu(2)))
-k_step(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status,
+k_step(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restrict__ status,
        const uint8_t *__restrict__ solid) {
   constexpr int TB = pair_block<M, S>;
   __shared__ S lds[stash_rows<M, S>][TB];
   const int blk = pair_block_order(blockIdx.x, gridDim.x);
   const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
   unsigned flags = 0;
-  pair_cell_step<M, S, TB, WALLS>(cur, nxt, g, rx, cell, lds, flags, solid);
+  pair_cell_step<M, S, TB, WALLS, AC>(cur, nxt, g, rx, cell, lds, flags, solid);
   if (flags) atomicOr(status, flags);
 }
 
@@ -389,9 +435,9 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
 // (s = f_i + f_inv(i) for the even moments, d = f_i - f_inv(i) for the odd
 // ones, and f^eq = w (E +- O) for the two members).  With WALLS, lanes of
 // solid cells leave at once.
-template <class M, class S, bool WALLS>
+template <class M, class S, bool WALLS, int AC = PULL>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, unsigned *__restrict__ status,
+k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restrict__ status,
            const uint8_t *__restrict__ solid) {
   const int blk = blockIdx.x;
   const int cell = blk * BLOCK + threadIdx.x;
@@ -413,10 +459,15 @@ k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, uns
     zo[sft + MAXD] = wrap_back(z, sft, g.nz) * static_cast<int>(nxny);
   }
   S f[M::Q];
+  const int own = static_cast<int>(row0) + x;
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Point P = M::P[i];
-    f[i] = load_at(cur + (i * g.stride + yo[P.ty + MAXD] + zo[P.tz + MAXD]), xo[P.tx + MAXD]);
+    if constexpr (AC == AA_EVEN)
+      f[i] = load_at(cur + i * g.stride, own);
+    else
+      f[i] = load_at(cur + ((AC == AA_ODD ? i ^ 1 : i) * g.stride + yo[P.ty + MAXD] + zo[P.tz + MAXD]),
+                     xo[P.tx + MAXD]);
   });
   // keep the phases apart: interleaving them raises the register peak
   __builtin_amdgcn_sched_barrier(0);
@@ -426,21 +477,37 @@ k_step_row(const S *__restrict__ cur, S *__restrict__ nxt, Geom g, Relax rx, uns
   const unsigned flags = landau_frame(m, fr);
   const double tau = relaxation_time<M>(rx, fr.n, fr.T);
   __builtin_amdgcn_sched_barrier(0);
-  const int own = static_cast<int>(row0) + x;
-  relax_cell<M>(f, fr, tau, [&](auto I, S v) {
-    constexpr int i = decltype(I)::value;
-    store_at(nxt + i * g.stride, own, v);
-  });
+  if constexpr (AC == AA_ODD) {
+    // stores to x + theta_i; the x offsets are computed again here rather
+    // than kept live through the arithmetic
+    int xs = x;
+    asm volatile("" : "+v"(xs));
+    int xf[2 * MAXD + 1];
+#pragma unroll
+    for (int sft = -MAXD; sft <= MAXD; ++sft) xf[sft + MAXD] = wrap_back(xs, sft, g.nx);
+    relax_cell<M>(f, fr, tau, [&](auto I, S v) {
+      constexpr int i = decltype(I)::value;
+      constexpr Point P = M::P[i];
+      store_at(nxt + (i * g.stride + yo[MAXD - P.ty] + zo[MAXD - P.tz]), xf[MAXD - P.tx], v);
+    });
+  } else {
+    relax_cell<M>(f, fr, tau, [&](auto I, S v) {
+      constexpr int i = decltype(I)::value;
+      store_at(nxt + (AC == AA_EVEN ? i ^ 1 : i) * g.stride, own, v);
+    });
+  }
   if (flags) atomicOr(status, flags);
 }
 
 // Initial state: local equilibrium of (n, eps, v) in every cell, stored so
 // that the next gather returns it (scatter to x - theta_i).
+// With aa != 0 the state is written in the natural AA layout (slot (i, x) =
+// f_i(x)) instead of scattered for the pull.
 template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, const double *__restrict__ eps_,
                                                 const double *__restrict__ vx_, const double *__restrict__ vy_,
                                                 const double *__restrict__ vz_, S *__restrict__ cur, Geom g,
-                                                unsigned *__restrict__ status) {
+                                                unsigned *__restrict__ status, int aa) {
   const int cell = blockIdx.x * BLOCK + threadIdx.x;
   if (cell >= g.cells) return;
   int x, y, z;
@@ -463,8 +530,13 @@ __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, c
       constexpr Point P = M::P[2 * k];
       CT E, O;
       shell_eval<M, 2 * k, CT>(s, E, O);
-      store_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>(), S(P.w * (E + O)));
-      store_at(cur + (2 * k + 1) * g.stride, sh.back<-P.tx, -P.ty, -P.tz>(), S(P.w * (E - O)));
+      if (aa) {
+        store_at(cur + (2 * k) * g.stride, cell, S(P.w * (E + O)));
+        store_at(cur + (2 * k + 1) * g.stride, cell, S(P.w * (E - O)));
+      } else {
+        store_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>(), S(P.w * (E + O)));
+        store_at(cur + (2 * k + 1) * g.stride, sh.back<-P.tx, -P.ty, -P.tz>(), S(P.w * (E - O)));
+      }
     });
   });
   if (flags) atomicOr(status, flags);
@@ -476,7 +548,7 @@ template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom g, double *__restrict__ n_,
                                                 double *__restrict__ eps_, double *__restrict__ U_,
                                                 double *__restrict__ P_, unsigned *__restrict__ status,
-                                                const uint8_t *__restrict__ solid) {
+                                                const uint8_t *__restrict__ solid, int mode) {
   const int cell = blockIdx.x * BLOCK + threadIdx.x;
   if (cell >= g.cells) return;
   if (solid && solid[cell]) {
@@ -491,7 +563,7 @@ __global__ void __launch_bounds__(BLOCK) k_read(const S *__restrict__ cur, Geom 
   cell_coords(cell, g, x, y, z);
   const Shifts sh(x, y, z, g);
   S f[M::Q];
-  gather<M>(cur, g, sh, f);
+  gather<M>(cur, g, sh, f, mode, cell);
   const Moments m = moments<M>(f);
   Frame fr;
   const unsigned flags = landau_frame(m, fr);

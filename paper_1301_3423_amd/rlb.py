@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, ENONPHYS, EHIP, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 TAU_FIXED, TAU_ETA_S = 0, 1
 ORDER3, ORDER2 = 3, 2
+PATTERN_AB, PATTERN_AA = 0, 1
 FLAG_NONFINITE, FLAG_NONPHYSICAL, FLAG_LANDAU = 1, 2, 4
 MAX_Q = 128
 
@@ -57,7 +58,8 @@ class Lattice(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
-                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double), ("order", ctypes.c_int32)]
+                ("tau", ctypes.c_double), ("eta_s", ctypes.c_double), ("order", ctypes.c_int32),
+                ("pattern", ctypes.c_int32)]
 
 
 class Tube(ctypes.Structure):
@@ -93,7 +95,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64
         L.rlb_lattice_info.argtypes = [i32, ctypes.POINTER(Lattice)]
-        L.rlb_state_bytes.argtypes = [i32, i32, i32, i32, i32]
+        L.rlb_state_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
         L.rlb_state_bytes.restype = ctypes.c_size_t
         L.rlb_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, vp]
         L.rlb_init_fields.argtypes = [vp, vp, vp, vp, vp, vp, i32]
@@ -149,8 +151,16 @@ def lattice_info(order=ORDER3):
                 shell=np.array(lat.shell[:q]), sha256=lat.sha256.decode())
 
 
-def state_bytes(nx, ny, nz, precision="fp64", order=ORDER3):
-    return lib().rlb_state_bytes(nx, ny, nz, _prec(precision), int(order))
+def state_bytes(nx, ny, nz, precision="fp64", order=ORDER3, pattern="ab"):
+    return lib().rlb_state_bytes(nx, ny, nz, _prec(precision), int(order), _pattern(pattern))
+
+
+def _pattern(p):
+    if p in ("ab", PATTERN_AB):
+        return PATTERN_AB
+    if p in ("aa", PATTERN_AA):
+        return PATTERN_AA
+    raise ValueError("pattern must be 'ab' or 'aa'")
 
 
 def _prec(p):
@@ -169,12 +179,14 @@ def _stream_ptr(stream):
 
 class Solver:
     """One periodic nx x ny x nz box on the current HIP device, third-order
-    (order=3) or second-order (order=2) model.
+    (order=3) or second-order (order=2) model, two population buffers
+    (pattern="ab") or one updated in place (pattern="aa").
 
     Device memory is a torch uint8 tensor owned by this object; the solver
     runs on `stream` (default: torch's current stream at construction)."""
 
-    def __init__(self, nx, ny, nz, precision="fp64", tau=None, eta_s=None, stream=None, device=None, order=ORDER3):
+    def __init__(self, nx, ny, nz, precision="fp64", tau=None, eta_s=None, stream=None, device=None, order=ORDER3,
+                 pattern="ab"):
         import torch
         if (tau is None) == (eta_s is None):
             raise ValueError("give exactly one of tau, eta_s")
@@ -182,13 +194,14 @@ class Solver:
         self.cells = nx * ny * nz
         self.precision = precision
         self.order = int(order)
+        self.pattern = _pattern(pattern)
         cfg = Config(nx, ny, nz, _prec(precision), TAU_FIXED if tau is not None else TAU_ETA_S,
                      float(tau) if tau is not None else 0.0, float(eta_s) if eta_s is not None else 0.0,
-                     self.order)
+                     self.order, self.pattern)
         self.cfg = cfg
-        nbytes = state_bytes(nx, ny, nz, precision, self.order)
+        nbytes = state_bytes(nx, ny, nz, precision, self.order, self.pattern)
         if nbytes == 0:
-            raise RLBError(EINVAL, "invalid lattice size, precision or order")
+            raise RLBError(EINVAL, "invalid lattice size, precision, order or pattern")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -17,3 +17,9 @@ def pytest_configure(config):
 def lat():
     import oracle
     return oracle.load_lattice()
+
+
+@pytest.fixture(scope="session")
+def lat2():
+    from oracle.lattice import model_lattice
+    return model_lattice(2)

@@ -1,0 +1,129 @@
+"""The in-place AA streaming pattern against the two-buffer (AB) pull.
+
+Both patterns run the same per-cell arithmetic on the same values, so after
+every step the macroscopic fields of an AA solver equal those of an AB
+solver bit for bit, after even steps (natural AA layout) and after odd steps
+(swapped layout).  A read-after-write race in the in-place update, or a
+wrong slot in either half-step, would break that equality.  The oracle is
+checked directly as well, to the usual parity bar."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from gpu_util import field_errors, note
+from oracle import rlb as orlb
+from paper_1301_3423_amd import inputs, rlb
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+SHAPES = [
+    (13, 11, 7),     # ragged tail of the two-lane kernel
+    (5, 4, 3),       # every axis below the largest displacement: wrap beyond the edge
+    (9, 1, 17),      # a degenerate axis
+    (64, 3, 5),      # whole-wavefront rows (float32 one-lane kernel), small y and z
+    (128, 12, 9),
+]
+
+
+def _same(a, b):
+    for k in ("n", "eps", "P"):
+        if not np.array_equal(a[k], b[k]):
+            return False
+    return np.array_equal(a["U"], b["U"])
+
+
+@pytest.mark.parametrize("order", [3, 2])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_aa_equals_ab_every_step(shape, precision, order):
+    note("case AA vs AB order=%d shape=%s precision=%s" % (order, shape, precision))
+    fields = inputs.random_box(*shape, 0.5, seed=sum(shape) + order)
+    ab = rlb.Solver(*shape, precision=precision, eta_s=0.2, order=order, pattern="ab")
+    aa = rlb.Solver(*shape, precision=precision, eta_s=0.2, order=order, pattern="aa")
+    ab.init_fields(*fields)
+    aa.init_fields(*fields)
+    assert _same(ab.read_fields(), aa.read_fields())
+    for t in range(1, 6):
+        ab.step(1)
+        aa.step(1)
+        assert _same(ab.read_fields(), aa.read_fields()), "step %d" % t
+    assert aa.status() == (0, 5)
+    c_ab, c_aa = ab.conserved(), aa.conserved()
+    assert np.max(np.abs(c_ab - c_aa)) < 1e-13 * abs(c_ab[1])
+
+
+@pytest.mark.parametrize("order", [3, 2])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("steps", [7, 8])
+def test_aa_matches_oracle(lat, lat2, order, precision, steps):
+    shape = (40, 36, 33)   # 47520 cells: many blocks, ragged tail
+    note("case AA vs oracle order=%d precision=%s steps=%d" % (order, precision, steps))
+    fields = inputs.random_box(*shape, 0.5, seed=41)
+    s = rlb.Solver(*shape, precision=precision, eta_s=0.2, order=order, pattern="aa")
+    s.init_fields(*fields)
+    s.step(steps)
+    gpu = s.read_fields()
+    o = orlb.Solver(*shape, lat=lat if order == 3 else lat2, order=order, eta_s=0.2)
+    o.init_fields(*fields)
+    o.step(steps)
+    err = field_errors(gpu, o.read_fields())
+    note("errors %s" % {k: "%.2e" % v for k, v in err.items()})
+    assert s.status() == (0, steps)
+    assert max(err.values()) <= TOL[precision], err
+
+
+def test_aa_conserves_on_device():
+    fields = inputs.random_box(20, 18, 16, 0.5, seed=2)
+    s = rlb.Solver(20, 18, 16, precision="fp64", eta_s=0.2, pattern="aa")
+    s.init_fields(*fields)
+    c0 = s.conserved()
+    for steps in (1, 1, 97):      # odd t, even t, odd t
+        s.step(steps)
+        c1 = s.conserved()
+        assert np.max(np.abs(c1 - c0)) < 1e-13 * abs(c0[1]), (s.status(), c1 - c0)
+
+
+@pytest.mark.parametrize("split", [3, 4])
+def test_aa_checkpoint_resumes_bitwise(split):
+    shape = (24, 16, 10)
+    fields = inputs.random_box(*shape, 0.5, seed=5)
+    ref = rlb.Solver(*shape, precision="fp64", tau=0.9, pattern="aa")
+    ref.init_fields(*fields)
+    ref.step(7)
+    a = rlb.Solver(*shape, precision="fp64", tau=0.9, pattern="aa")
+    a.init_fields(*fields)
+    a.step(split)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "aa.ckpt")
+        a.save(path)
+        b = rlb.Solver(*shape, precision="fp64", tau=0.9, pattern="aa")
+        b.load(path)
+        assert b.status() == (0, split)
+        b.step(7 - split)
+        assert _same(b.read_fields(), ref.read_fields())
+        # a checkpoint of the other pattern is refused
+        c = rlb.Solver(*shape, precision="fp64", tau=0.9, pattern="ab")
+        with pytest.raises(rlb.RLBError):
+            c.load(path)
+
+
+def test_aa_refuses_walls():
+    s = rlb.Solver(16, 16, 8, precision="fp64", tau=1.0, pattern="aa")
+    solid = np.zeros((8, 16, 16), bool)
+    solid[:, :6] = True
+    with pytest.raises(rlb.RLBError):
+        s.set_walls(solid)
+
+
+def test_aa_halves_the_footprint():
+    """At 256^3 the AA state is one population buffer plus staging."""
+    for prec, b in (("fp64", 8), ("mixed", 4)):
+        ab = rlb.state_bytes(256, 256, 256, prec, 3, "ab")
+        aa = rlb.state_bytes(256, 256, 256, prec, 3, "aa")
+        cells = 256 ** 3
+        assert aa - 128 * cells * b - 56 * cells < 1 << 20
+        assert ab - 2 * 128 * cells * b < 1 << 20

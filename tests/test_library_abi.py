@@ -65,8 +65,21 @@ def test_state_bytes(order, q):
     assert b64 >= 2 * q * cells * 8 and b32 >= 2 * q * cells * 4
     assert b64 - 2 * q * cells * 8 < 2 * q * 64 * 8 + 8192
     assert rlb.state_bytes(0, 4, 4) == 0
-    assert rlb.lib().rlb_state_bytes(4, 4, 4, 7, order) == 0
-    assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, 1) == 0          # no first-order model
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 7, order, 0) == 0
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, 1, 0) == 0       # no first-order model
+    assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, order, 2) == 0   # no third pattern
+
+
+@pytest.mark.parametrize("order,q", [(3, 128), (2, 66)])
+def test_state_bytes_aa_holds_one_buffer(order, q):
+    """AA: one population buffer plus 7 doubles of staging per cell."""
+    cells = 24 * 20 * 16
+    for prec, b in (("fp64", 8), ("mixed", 4)):
+        ab = rlb.state_bytes(24, 20, 16, prec, order, "ab")
+        aa = rlb.state_bytes(24, 20, 16, prec, order, "aa")
+        assert aa >= q * cells * b + 7 * 8 * cells
+        assert aa - (q * cells * b + 7 * 8 * cells) < q * 64 * b + 8192
+        assert abs((ab - aa) - (q * cells * b - 7 * 8 * cells)) < q * 64 * b + 256
 
 
 def test_batch_and_request_bytes_follow_the_model():
@@ -103,6 +116,9 @@ def test_create_rejects_bad_arguments():
     cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_FIXED, 1.0, 0.0, 1)   # order 1 does not exist
     assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
     assert b"order" in L.rlb_last_error()
+    cfg = rlb.Config(8, 8, 8, rlb.FP64, rlb.TAU_FIXED, 1.0, 0.0, 3, 2)   # pattern 2 does not exist
+    assert L.rlb_create(ctypes.byref(h), ctypes.byref(cfg), fake, 1 << 40, None) == rlb.EINVAL
+    assert b"pattern" in L.rlb_last_error()
     assert L.rlb_step(None, 1) == rlb.EINVAL
 
 
