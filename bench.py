@@ -26,11 +26,20 @@ HBM_PEAK_GBS = 8000.0
 Q_OF_ORDER = {3: 128, 2: 66}
 
 
-def kernel_name(order, precision, edge):
-    """The step kernel the library launches for a box of this edge."""
+ACCESS = {"pull": 0, "aa_even": 1, "aa_odd": 2}   # the kernels' access template argument
+
+
+def kernel_name(order, precision, edge, access="pull"):
+    """The step kernel the library launches for a box of this edge (two-buffer
+    pull, or the even or odd step of the in-place AA pattern)."""
+    a = ACCESS[access]
+    two_lane = precision == "fp64" or edge % 64 != 0
+    if access == "aa_odd" and two_lane and edge > 6:
+        a = 3   # the odd step's form for boxes wider than the largest shift
     if precision == "fp64":
-        return "k_step<Model<%d>, double, false>" % order
-    return ("k_step_row<Model<%d>, float, false>" if edge % 64 == 0 else "k_step<Model<%d>, float, false>") % order
+        return "k_step<Model<%d>, double, false, %d>" % (order, a)
+    return ("k_step_row<Model<%d>, float, false, %d>" if edge % 64 == 0
+            else "k_step<Model<%d>, float, false, %d>") % (order, a)
 
 
 def parse():
@@ -374,9 +383,11 @@ def main():
             r = run_box(edge, prec, fields, args.steps, args.warmup, args.eta_s, pattern="aa")
             print("bench: AA %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
             same = all(np.array_equal(r["fields"][k], ab["fields"][k]) for k in ("n", "eps", "P", "U"))
+            traffic = {acc: profiled_traffic(kernel_name(3, prec, edge, acc), edge) for acc in ("aa_even", "aa_odd")}
             aa[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 4),
                         "vs_ab": round(ab["ms_per_step"] / r["ms_per_step"], 3),
                         "achieved_GBps": round(r["achieved_gbs"], 1), "fields_equal_ab": bool(same),
+                        "traffic_bytes_per_launch": traffic,
                         "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
     tubes = {}
     if not args.no_tubes:

@@ -20,6 +20,11 @@ HIP_FLAGS = [
     "-shared",
     # no packed fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse only within one source expression: the rounding of
+    # every kernel then follows the source alone, not how the compiler splits
+    # the code into blocks, so kernel variants that run the same arithmetic
+    # (two-buffer pull and in-place AA steps) give identical bits
+    "-ffp-contract=on",
     "-I", os.path.join(REPO, "include"),
 ]
 
@@ -38,6 +43,7 @@ def source_digest():
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(a for a in HIP_FLAGS if os.sep not in a).encode())
     return h.hexdigest()
 
 

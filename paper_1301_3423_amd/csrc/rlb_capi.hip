@@ -137,7 +137,9 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
         static_cast<const double *>(in), static_cast<double *>(out), g, r, s->status, solid);
   } else if (s->cfg.nx % 64 == 0) {
     const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
-    rlb::k_step_row<M, float, WALLS, AC><<<grid, block, 0, s->stream>>>(
+    // rows of 64 cells: x is always wide, and the row kernel has one odd form
+    constexpr int RAC = AC == rlb::AA_ODD_WIDE ? rlb::AA_ODD : AC;
+    rlb::k_step_row<M, float, WALLS, RAC><<<grid, block, 0, s->stream>>>(
         static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
   } else {
     constexpr int TB = rlb::pair_block<M, float>;
@@ -172,6 +174,8 @@ int launch_step(rlb_solver *s) {
       launch_step_kernels<M, true, rlb::PULL>(s, g, r);
     else if (ac == rlb::AA_EVEN)
       launch_step_kernels<M, false, rlb::AA_EVEN>(s, g, r);
+    else if (ac == rlb::AA_ODD && g.nx > rlb::MAXD)
+      launch_step_kernels<M, false, rlb::AA_ODD_WIDE>(s, g, r);
     else if (ac == rlb::AA_ODD)
       launch_step_kernels<M, false, rlb::AA_ODD>(s, g, r);
     else
