@@ -127,3 +127,28 @@ def test_aa_halves_the_footprint():
         cells = 256 ** 3
         assert aa - 128 * cells * b - 56 * cells < 1 << 20
         assert ab - 2 * 128 * cells * b < 1 << 20
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_aa_equals_ab_at_256cube(precision):
+    """The benchmark's box and launch configuration: after an odd and an even
+    number of steps the AA fields equal the AB fields bit for bit (the AB
+    path is pinned to the oracle at this size on sampled cells)."""
+    import torch
+    shape = (256, 256, 256)
+    note("case AA vs AB 256^3 precision=%s" % precision)
+    fields = inputs.random_box(*shape, 0.6, seed=3)
+    ab = rlb.Solver(*shape, precision=precision, eta_s=0.5, pattern="ab")
+    ab.init_fields(*fields)
+    ref = []
+    for steps in (3, 1):
+        ab.step(steps)
+        ref.append(ab.read_fields())
+    del ab
+    torch.cuda.empty_cache()
+    aa = rlb.Solver(*shape, precision=precision, eta_s=0.5, pattern="aa")
+    aa.init_fields(*fields)
+    for steps, r in zip((3, 1), ref):
+        aa.step(steps)
+        assert _same(aa.read_fields(), r), "t=%d" % aa.status()[1]
+    assert aa.status() == (0, 4)
