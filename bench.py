@@ -159,6 +159,45 @@ def run_box(edge, precision, fields, steps, warmup, eta_s, order=3, solid=None, 
     return out
 
 
+def run_largest_aa(precision, steps, warmup, vmax, eta_s, frac=0.92):
+    """The largest box of this precision one GPU holds with the AA pattern
+    (edge a multiple of 64, within the library's size cap), fields generated
+    on the device."""
+    import gc
+    import torch
+    from paper_1301_3423_amd import inputs, rlb
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    per_cell = rlb.state_bytes(64, 64, 64, precision, 3, "aa") / 64 ** 3 + 40
+    edge = int((frac * free / per_cell) ** (1.0 / 3.0)) // 64 * 64
+    while edge > 64 and rlb.state_bytes(edge, edge, edge, precision, 3, "aa") == 0:
+        edge -= 64
+    fields, _ = inputs.random_box_device(edge, edge, edge, vmax, 3)
+    torch.cuda.empty_cache()
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, pattern="aa")
+    s.init_fields(*fields)
+    s.release_inputs()
+    del fields
+    torch.cuda.empty_cache()
+    c0 = s.conserved()
+    ms, wall = time_steps(s, steps, warmup)
+    c1 = s.conserved()
+    flags, t = s.status()
+    cells = edge ** 3
+    b = 8 if precision == "fp64" else 4
+    out = dict(edge=edge, cells=cells, value=round(cells / (ms * 1e-3) / 1e6, 2), unit="MLUPS",
+               ms_per_step=round(ms, 4), achieved_GBps=round(2 * 128 * b * cells / (ms * 1e-3) / 1e9, 1),
+               state_GB=round(rlb.state_bytes(edge, edge, edge, precision, 3, "aa") / 1e9, 1),
+               two_buffer_GB=round(rlb.state_bytes(edge, edge, edge, precision, 3, "ab") / 1e9, 1),
+               gpu_GB=round(total / 1e9, 1), steps=steps, status_flags=flags,
+               conservation_drift=float(np.max(np.abs(c1 - c0)) / abs(c0[1])))
+    del s
+    gc.collect()
+    torch.cuda.empty_cache()
+    return out
+
+
 def field_error_summary(a, b):
     """Max-norm relative error per field; the 4-velocity is compared as a
     4-vector (all components against max |U^mu|), as in the parity tests."""
@@ -389,6 +428,11 @@ def main():
                         "achieved_GBps": round(r["achieved_gbs"], 1), "fields_equal_ab": bool(same),
                         "traffic_bytes_per_launch": traffic,
                         "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
+    largest = None
+    if not args.no_aa and not args.no_fp64:
+        largest = run_largest_aa("fp64", min(args.steps, 20), 2, args.vmax, args.eta_s)
+        print("bench: largest AA fp64 box %d^3: %.1f MLUPS" % (largest["edge"], largest["value"]),
+              file=sys.stderr, flush=True)
     tubes = {}
     if not args.no_tubes:
         for prec in ("fp64", "mixed"):
@@ -448,6 +492,11 @@ def main():
     if aa:
         line["aa_pattern"] = {"workload": "the same %d^3 box, fields and steps, third order, one population "
                                           "buffer updated in place (AA pattern) instead of two" % edge, **aa}
+    if largest is not None:
+        line["aa_largest_fp64"] = {
+            "workload": "the largest float64 third-order box this GPU holds with the AA pattern (%d^3, random "
+                        "fields generated on the device, same recipe); the two-buffer layout would need "
+                        "%.0f GB" % (largest["edge"], largest["two_buffer_GB"]), **largest}
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

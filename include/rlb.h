@@ -75,8 +75,9 @@ extern "C" {
  * population i in the slot of its inverse), odd steps read the inverse slots
  * of the neighbours x - theta_i and write to x + theta_i, which restores the
  * natural layout.  Same arithmetic and results, half the population memory
- * (plus 56 bytes per cell of staging), so larger boxes fit: about 512^3 in
- * float64 with the third-order model on 288 GB.  Walls need AB. */
+ * (plus 56 bytes per cell of staging), so larger boxes fit: 576^3 in
+ * float64 with the third-order model needs 206 GB with AA and 391 GB with
+ * AB.  Walls need AB. */
 #define RLB_PATTERN_AB 0
 #define RLB_PATTERN_AA 1
 
@@ -125,7 +126,8 @@ int rlb_lattice_info(int32_t order, rlb_lattice_t *out);
 
 /* ---- one periodic box ---------------------------------------------------- */
 typedef struct rlb_config {
-  int32_t nx, ny, nz; /* lattice size, all periodic; each >= 1            */
+  int32_t nx, ny, nz; /* lattice size, all periodic; each >= 1, and       */
+                      /* nx*ny*nz <= 2^28 - 2^16 (268,369,920 cells)      */
   int32_t precision;  /* RLB_FP64 or RLB_MIXED                            */
   int32_t tau_mode;   /* RLB_TAU_FIXED or RLB_TAU_ETA_S                   */
   double tau;         /* relaxation time when tau_mode == RLB_TAU_FIXED   */

@@ -65,9 +65,11 @@ decltype(auto) with_model(int order, F &&f) {
 bool valid_dims(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   const int64_t c = static_cast<int64_t>(nx) * ny * nz;
-  // the kernels address (member offset + cell) * 8 bytes with 32-bit
-  // unsigned offsets: (stride + cells) * 8 < 2^32 for cells <= 2^27
-  return c <= (int64_t(1) << 27);
+  // the two-lane kernels address (member offset + cell) * 8 bytes with
+  // 32-bit unsigned offsets, the member offset being at most one stride
+  // (<= cells + 64 elements): (2 cells + 64) * 8 < 2^32 for cells below
+  // 2^28 - 64; the cap keeps a margin
+  return c <= (int64_t(1) << 28) - (int64_t(1) << 16);
 }
 
 } // namespace

@@ -47,10 +47,15 @@ def _field(modes, nx, ny, nz):
     return (A @ B).real.reshape(nz, ny, nx)
 
 
+def box_modes(seed):
+    """The Fourier modes of random_box for this seed: (vx, vy, vz, theta)."""
+    rng = np.random.default_rng(seed)
+    return tuple(_modes(rng) for _ in range(4))
+
+
 def random_box(nx, ny, nz, v_max, seed):
     """Returns n, eps, vx, vy, vz for a periodic box."""
-    rng = np.random.default_rng(seed)
-    mvx, mvy, mvz, mth = (_modes(rng) for _ in range(4))
+    mvx, mvy, mvz, mth = box_modes(seed)
     gx, gy, gz, gth = (_field(m, nx, ny, nz) for m in (mvx, mvy, mvz, mth))
     norm = np.sqrt(gx * gx + gy * gy + gz * gz).max()
     s = v_max / norm if norm > 0 else 0.0
@@ -123,3 +128,51 @@ def request_fields(req, cache=None):
     if cache is not None:
         cache[e] = f
     return f
+
+
+def _field_torch(modes, nx, ny, nz, device):
+    """_field evaluated on a device with torch (complex128)."""
+    import torch
+    def ex(k, n):
+        return torch.exp(2j * np.pi * k * torch.arange(n, device=device, dtype=torch.float64) / n)
+    A = torch.stack([(complex(a * np.exp(1j * ph)) * ex(int(k[2]), nz))[:, None] * ex(int(k[1]), ny)[None, :]
+                     for k, a, ph in modes], dim=-1).reshape(nz * ny, len(modes))
+    B = torch.stack([ex(int(k[0]), nx) for k, a, ph in modes], dim=0)
+    return (A @ B).real.contiguous().reshape(nz, ny, nx)
+
+
+def random_box_device(nx, ny, nz, v_max, seed, device="cuda"):
+    """random_box generated on a device (same modes, same formulas; equal to
+    random_box up to rounding), for boxes too large to build on the host.
+    Returns the five float64 tensors and the two normalisations used,
+    (v_max / max |g_v|, max |g_theta|), so that field_window can rebuild any
+    part of the same fields on the host."""
+    import torch
+    mvx, mvy, mvz, mth = box_modes(seed)
+    gx, gy, gz = (_field_torch(m, nx, ny, nz, device) for m in (mvx, mvy, mvz))
+    norm = float(torch.sqrt(gx * gx + gy * gy + gz * gz).max())
+    sv = v_max / norm if norm > 0 else 0.0
+    gx.mul_(sv), gy.mul_(sv), gz.mul_(sv)
+    gth = _field_torch(mth, nx, ny, nz, device)
+    gmax = float(gth.abs().max())
+    T = gth.mul_(0.1 / (gmax if gmax > 0 else 1.0)).add_(1.0)
+    n = T ** 3
+    eps = 3.0 * T ** 4
+    del T
+    return (n, eps, gx, gy, gz), (sv, gmax)
+
+
+def field_window(seed, shape, norms, idx):
+    """n, eps, vx, vy, vz of random_box_device's fields on the cells
+    idx = (z, y, x) (index arrays, combined as an open grid), evaluated
+    directly from the modes on the host."""
+    nx, ny, nz = shape
+    sv, gmax = norms
+    z, y, x = np.ix_(*idx)
+    def g(modes):
+        return sum(a * np.cos(2 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + ph)
+                   for k, a, ph in modes)
+    mvx, mvy, mvz, mth = box_modes(seed)
+    vx, vy, vz = g(mvx) * sv, g(mvy) * sv, g(mvz) * sv
+    T = 1.0 + 0.1 * g(mth) / (gmax if gmax > 0 else 1.0)
+    return T ** 3, 3.0 * T ** 4, vx, vy, vz

@@ -234,6 +234,13 @@ class Solver:
                 raise ValueError("field has %d values, expected %d" % (h.size, self.cells))
         check(lib().rlb_init_fields(self._h, *[ctypes.c_void_p(h.ctypes.data) for h in hs], 0))
 
+    def release_inputs(self):
+        """Wait until the solver's stream has consumed device fields given to
+        init_fields, then drop the references kept to them."""
+        if getattr(self, "_keep", None) is not None:
+            self.stream.synchronize()
+            self._keep = None
+
     def step(self, nsteps=1):
         check(lib().rlb_step(self._h, int(nsteps)))
 

@@ -152,3 +152,59 @@ def test_aa_equals_ab_at_256cube(precision):
         aa.step(steps)
         assert _same(aa.read_fields(), r), "t=%d" % aa.status()[1]
     assert aa.status() == (0, 4)
+
+
+def largest_aa_edge(precision, reserve_per_cell=40, frac=0.92):
+    """Largest multiple of 64 whose AA box (plus its device input fields)
+    fits in the free memory of the current device, within the library's
+    size cap."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    per_cell = rlb.state_bytes(64, 64, 64, precision, 3, "aa") / 64 ** 3 + reserve_per_cell
+    edge = int((frac * free / per_cell) ** (1.0 / 3.0)) // 64 * 64
+    while edge > 64 and rlb.state_bytes(edge, edge, edge, precision, 3, "aa") == 0:
+        edge -= 64
+    return edge
+
+
+def test_aa_largest_box_matches_oracle_on_sampled_cells(lat):
+    """The largest float64 box one GPU holds with the AA pattern (576^3 on
+    288 GB, where the two-buffer layout would need 391 GB): after two steps
+    sampled cells, corners included, agree with the oracle run on the
+    periodic 25^3 window of the initial fields around each of them."""
+    import torch
+    K, W = 2, 25
+    edge = largest_aa_edge("fp64")
+    shape = (edge, edge, edge)
+    note("case AA largest box %d^3 fp64 (AA %.1f GB, AB would need %.1f GB)" % (
+        edge, rlb.state_bytes(*shape, "fp64", 3, "aa") / 1e9, rlb.state_bytes(*shape, "fp64", 3, "ab") / 1e9))
+    fields, norms = inputs.random_box_device(*shape, 0.6, 3)
+    torch.cuda.empty_cache()
+    s = rlb.Solver(*shape, precision="fp64", eta_s=0.5, pattern="aa")
+    s.init_fields(*fields)
+    s.release_inputs()
+    del fields
+    torch.cuda.empty_cache()
+    s.step(K)
+    out = s.read_fields()
+    assert s.status() == (0, K)
+    del s
+    rng = np.random.default_rng(edge)
+    pts = [(0, 0, 0), (edge - 1, edge - 1, edge - 1), (edge // 2, 0, edge - 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, edge, 3)) for _ in range(2)]
+    mid = 6 * K * (W * W + W + 1)
+    for c in pts:
+        idx = [np.arange(ci - 6 * K, ci + 6 * K + 1) % edge for ci in c]
+        win = inputs.field_window(3, shape, norms, idx)
+        o = orlb.Solver(W, W, W, lat=lat, eta_s=0.5)
+        o.init_fields(*win)
+        o.step(K)
+        ref = o.read_fields()
+        flat = (c[0] * edge + c[1]) * edge + c[2]
+        U0 = ref["U"][0, mid]
+        errs = [abs(out[k][flat] - ref[k][mid]) / ref[k][mid] for k in ("n", "eps", "P")]
+        errs += [abs(out["U"][j, flat] - ref["U"][j, mid]) / U0 for j in range(4)]
+        assert max(errs) <= 1e-12, (c, errs)

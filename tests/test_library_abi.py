@@ -68,6 +68,9 @@ def test_state_bytes(order, q):
     assert rlb.lib().rlb_state_bytes(4, 4, 4, 7, order, 0) == 0
     assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, 1, 0) == 0       # no first-order model
     assert rlb.lib().rlb_state_bytes(4, 4, 4, 0, order, 2) == 0   # no third pattern
+    # boxes up to 2^28 - 2^16 cells: 640^3 is accepted, 2^28 cells are not
+    assert rlb.state_bytes(640, 640, 640, "fp64", order, "aa") > 0
+    assert rlb.state_bytes(1024, 512, 512, "mixed", order) == 0
 
 
 @pytest.mark.parametrize("order,q", [(3, 128), (2, 66)])
