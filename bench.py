@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-second-order", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-aa", action="store_true")
+    ap.add_argument("--no-largest", action="store_true", help="skip the largest-box AA leg")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
@@ -429,7 +430,7 @@ def main():
                         "traffic_bytes_per_launch": traffic,
                         "status_flags": r["flags"], "conservation_drift": r["conservation_drift"]}
     largest = None
-    if not args.no_aa and not args.no_fp64:
+    if not args.no_aa and not args.no_fp64 and not args.no_largest:
         largest = run_largest_aa("fp64", min(args.steps, 20), 2, args.vmax, args.eta_s)
         print("bench: largest AA fp64 box %d^3: %.1f MLUPS" % (largest["edge"], largest["value"]),
               file=sys.stderr, flush=True)
