@@ -360,9 +360,19 @@ def cpu_baseline(vmax, eta_s):
         t0 = time.perf_counter()
         o.step(steps)
         dt = time.perf_counter() - t0
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=edge ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample="%d^3 box, same field generator (v_max %.2g, eta/s %.2g), %d steps, numpy FP64, "
-                       "BLAS limited to 1 thread; %.1f s" % (edge, vmax, eta_s, steps, dt))
+                       "BLAS limited to 1 thread (more threads do not speed the oracle up: its time is in "
+                       "element-wise array code); %.1f s on %s, %d CPUs visible"
+                       % (edge, vmax, eta_s, steps, dt, cpu, os.cpu_count() or 0))
 
 
 def main():
