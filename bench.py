@@ -232,8 +232,10 @@ def run_tubes(precision, ntubes=512, steps=500, seed=4):
     lu = sum(t["N"] for t in spec) * steps
     flags = [b.status(j)[0] for j in range(len(spec))]
     bpl = 2 * Q_OF_ORDER[3] * (8 if precision == "fp64" else 4)
+    fields = [b.read_tube(j) for j in range(len(spec))]
     return dict(mlups=lu / (ms * 1e-3) / 1e6, ms=ms, cells=sum(t["N"] for t in spec),
-                achieved_gbs=lu * bpl / (ms * 1e-3) / 1e9, tubes_flagged=sum(1 for f in flags if f))
+                achieved_gbs=lu * bpl / (ms * 1e-3) / 1e9, tubes_flagged=sum(1 for f in flags if f),
+                flags=flags, fields=fields)
 
 
 def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
@@ -445,9 +447,11 @@ def main():
         print("bench: largest AA fp64 box %d^3: %.1f MLUPS" % (largest["edge"], largest["value"]),
               file=sys.stderr, flush=True)
     tubes = {}
+    tube_runs = {}
     if not args.no_tubes:
         for prec in ("fp64", "mixed"):
             r = run_tubes(prec)
+            tube_runs[prec] = r
             print("bench: tubes %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
             tubes[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "launch_ms": round(r["ms"], 3),
                            "achieved_GBps": round(r["achieved_gbs"], 1), "cells": r["cells"],
@@ -512,6 +516,14 @@ def main():
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",
                          **tubes}
+        if len(tube_runs) == 2:
+            a, b = tube_runs["mixed"], tube_runs["fp64"]
+            errs = [max(field_error_summary(fa, fb).values())
+                    for fa, fb, ga, gb in zip(a["fields"], b["fields"], a["flags"], b["flags"]) if not (ga or gb)]
+            line["tubes"]["per_tube_error_mixed_vs_fp64"] = {
+                "tubes": len(errs), "max": float("%.3e" % max(errs)), "median": float("%.3e" % np.median(errs)),
+                "note": "max-norm relative error over n, eps, U, P of each unflagged tube after 502 steps; the "
+                        "float64 tube path is pinned to the oracle in the tests"}
     line["riemann_fp64"] = riemann
     if serving is not None:
         line["serving"] = serving
