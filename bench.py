@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-aa", action="store_true")
     ap.add_argument("--no-largest", action="store_true", help="skip the largest-box AA leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the full-length runs of the 128^3 float64 and 256^3 mixed configurations")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (for calibrating traffic counters)")
@@ -197,6 +199,24 @@ def run_largest_aa(precision, steps, warmup, vmax, eta_s, frac=0.92):
     gc.collect()
     torch.cuda.empty_cache()
     return out
+
+
+def run_long(edge, precision, fields, steps, eta_s):
+    """`steps` steps from the given fields; fields, status and conservation
+    drift at the end (no timing)."""
+    from paper_1301_3423_amd import rlb
+    s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s)
+    s.init_fields(*fields)
+    c0 = s.conserved()
+    t0 = time.perf_counter()
+    s.step(steps)
+    out = s.read_fields()
+    wall = time.perf_counter() - t0
+    c1 = s.conserved()
+    flags, t = s.status()
+    del s
+    return dict(fields=out, flags=flags, t=t, wall_s=wall,
+                drift=[float(v) for v in (c1 - c0) / np.abs(c0[[0, 1, 1, 1, 1]])])
 
 
 def field_error_summary(a, b):
@@ -446,6 +466,29 @@ def main():
         largest = run_largest_aa("fp64", min(args.steps, 20), 2, args.vmax, args.eta_s)
         print("bench: largest AA fp64 box %d^3: %.1f MLUPS" % (largest["edge"], largest["value"]),
               file=sys.stderr, flush=True)
+    configs = {}
+    if not args.no_configs and not args.no_fp64:
+        from paper_1301_3423_amd import inputs as _inp
+        f2 = _inp.random_box(128, 128, 128, 0.5, seed=2)
+        r = run_long(128, "fp64", f2, 1000, 0.2)
+        configs["box_128cube_fp64_1000_steps"] = {
+            "workload": "128^3 periodic box, float64, |v|<=0.5, T=1+-10%, eta/s=0.2 (seed 2), 1000 steps",
+            "mlups": round(128 ** 3 * 1000 / r["wall_s"] / 1e6, 1), "status_flags": r["flags"],
+            "drift_N0_T00_T0x_T0y_T0z": r["drift"],
+            "note": "drift = (final - initial) / |initial| for N^0 and T^00, and relative to T^00 for the "
+                    "momenta; MLUPS from the wall clock of the whole run including the read"}
+        del f2
+        print("bench: 128^3 fp64 1000 steps done", file=sys.stderr, flush=True)
+        rm = run_long(edge, "mixed", fields, 2000, args.eta_s)
+        rd = run_long(edge, "fp64", fields, 2000, args.eta_s)
+        configs["box_%dcube_mixed_vs_fp64_2000_steps" % edge] = {
+            "workload": "the %d^3 benchmark box, 2000 steps in each precision" % edge,
+            "max_rel": field_error_summary(rm["fields"], rd["fields"]),
+            "status_flags": [rm["flags"], rd["flags"]], "drift_mixed": rm["drift"], "drift_fp64": rd["drift"],
+            "note": "max-norm relative error of the mixed path against the float64 GPU path (pinned to the "
+                    "oracle at this size on sampled cells)"}
+        del rm, rd
+        print("bench: %d^3 2000-step comparison done" % edge, file=sys.stderr, flush=True)
     tubes = {}
     tube_runs = {}
     if not args.no_tubes:
@@ -512,6 +555,8 @@ def main():
             "workload": "the largest float64 third-order box this GPU holds with the AA pattern (%d^3, random "
                         "fields generated on the device, same recipe); the two-buffer layout would need "
                         "%.0f GB" % (largest["edge"], largest["two_buffer_GB"]), **largest}
+    if configs:
+        line["full_length_runs"] = configs
     if tubes:
         line["tubes"] = {"workload": "512 shock tubes 1x1xN, N~U{200..4000}, T_L/T_R~U(1.1,2), "
                                      "eta/s in {0.01,0.05,0.1,0.2,0.5}, 500 steps, one persistent launch",

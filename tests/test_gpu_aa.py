@@ -208,3 +208,25 @@ def test_aa_largest_box_matches_oracle_on_sampled_cells(lat):
         errs = [abs(out[k][flat] - ref[k][mid]) / ref[k][mid] for k in ("n", "eps", "P")]
         errs += [abs(out["U"][j, flat] - ref["U"][j, mid]) / U0 for j in range(4)]
         assert max(errs) <= 1e-12, (c, errs)
+
+
+def test_aa_reinit_at_odd_t_and_device_read():
+    """init_fields at an odd t starts again from the natural layout (t = 0),
+    and reading into device tensors gives the host read's values."""
+    shape = (24, 16, 10)
+    f1 = inputs.random_box(*shape, 0.5, seed=6)
+    f2 = inputs.random_box(*shape, 0.4, seed=7)
+    a = rlb.Solver(*shape, precision="fp64", eta_s=0.2, pattern="aa")
+    a.init_fields(*f1)
+    a.step(3)
+    a.init_fields(*f2)
+    assert a.status() == (0, 0)
+    a.step(5)
+    b = rlb.Solver(*shape, precision="fp64", eta_s=0.2, pattern="aa")
+    b.init_fields(*f2)
+    b.step(5)
+    host = a.read_fields()
+    assert _same(host, b.read_fields())
+    dev = a.read_fields(on_device=True)
+    for k in ("n", "eps", "P", "U"):
+        assert np.array_equal(dev[k].cpu().numpy(), host[k])
