@@ -1,7 +1,7 @@
 #!/bin/bash
 # Builds the library with AddressSanitizer and UBSan on its host code only
-# (device code is compiled as usual), and the driver abi_sanitize.cpp that
-# calls every C-ABI entry point, into tests/native/_build/.  Run the driver
+# (device code is compiled as usual), and the test program abi_sanitize.cpp that
+# calls every C-ABI entry point, into tests/native/_build/.  Run the program
 # on a machine with the GPU:
 #   ASAN_OPTIONS=detect_leaks=0:halt_on_error=1 UBSAN_OPTIONS=halt_on_error=1 \
 #     tests/native/_build/abi_sanitize
