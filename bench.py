@@ -123,6 +123,27 @@ def profiled_traffic(kernel, edge):
     return None
 
 
+def profile_fields(kernel):
+    """The key/value lines of the committed rocprofv3 summary of `kernel`
+    (the first one found), if it was taken of the current sources."""
+    from paper_1301_3423_amd.build import source_digest
+    prof_dir = os.path.join(REPO, "profiles")
+    if not os.path.isdir(prof_dir):
+        return None
+    digest = source_digest()
+    for name in sorted(os.listdir(prof_dir)):
+        if not name.endswith(".txt"):
+            continue
+        kv = {}
+        for line in open(os.path.join(prof_dir, name)):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel") == kernel and kv.get("source_sha256") == digest:
+            return kv
+    return None
+
+
 def time_steps(solver, steps, warmup):
     """Average per-step time (ms) from HIP events on the solver's stream."""
     import torch
@@ -496,9 +517,14 @@ def main():
             r = run_tubes(prec)
             tube_runs[prec] = r
             print("bench: tubes %s %.1f MLUPS" % (prec, r["mlups"]), file=sys.stderr, flush=True)
+            kv = profile_fields("k_tubes<Model<3>, %s>" % ("double" if prec == "fp64" else "float")) or {}
             tubes[prec] = {"value": round(r["mlups"], 2), "unit": "MLUPS", "launch_ms": round(r["ms"], 3),
                            "achieved_GBps": round(r["achieved_gbs"], 1), "cells": r["cells"],
-                           "tubes_flagged": r["tubes_flagged"]}
+                           "tubes_flagged": r["tubes_flagged"],
+                           "profiled_read_over_algorithmic": float(kv["read_over_algorithmic"])
+                           if "read_over_algorithmic" in kv else None,
+                           "profiled_write_over_algorithmic": float(kv["write_over_algorithmic"])
+                           if "write_over_algorithmic" in kv else None}
     riemann = run_riemann()
     serving = None
     if args.serve_requests > 0:
