@@ -341,6 +341,8 @@ def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
         "p50_tube_s": round(float(np.percentile(kinds.get("tube", [0]), 50)), 4),
         "p50_box_s": round(float(np.percentile(kinds.get("box", [0]), 50)), 4),
+        "p99_tube_s": round(float(np.percentile(kinds.get("tube", [0]), 99)), 4),
+        "p99_box_s": round(float(np.percentile(kinds.get("box", [0]), 99)), 4),
         "flagged": int(sum(1 for c in done if c["flags"])), "errors": int(sum(1 for c in done if c["rc"])),
         "rounds": int(rounds), "chunk_steps": chunk, "completed": len(done),
     }
