@@ -463,7 +463,11 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
   for (int64_t st = 0; st < d.steps; ++st) {
     const S *in = base + (cur ? d.off[1] : d.off[0]);
     S *out = base + (cur ? d.off[0] : d.off[1]);
+    // the first cell of this wavefront in a pass (wavefront-uniform): waves
+    // whose cells all lie beyond the tube skip the pass
+    const int wave0 = f64 ? (static_cast<int>(threadIdx.x) >> 6) * 32 : (static_cast<int>(threadIdx.x) & ~63);
     for (int c0 = 0; c0 < d.n; c0 += per_pass) {
+      if (c0 + wave0 >= d.n) continue;
       if constexpr (f64)
         pair_cell_step<M, S, TB>(in, out, g, rx, c0 + slot, lds, flags);
       else
