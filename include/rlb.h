@@ -157,7 +157,7 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
  * float64 values.  on_device = 0: host arrays, validated on the host
  * (RLB_ENONPHYS if any n <= 0, eps <= 0, |v| >= 1 or a value is not
  * finite; nothing is changed then) and copied through the idle population
- * buffer; the call returns after the copy.  on_device = 1: device arrays,
+ * buffer (AB) or the staging area (AA); the call returns after the copy.  on_device = 1: device arrays,
  * read on the stream; invalid cells raise RLB_FLAG_NONPHYSICAL instead.
  * The arrays may be released when the call returns (host) or when the
  * stream has passed this point (device). */
@@ -186,8 +186,9 @@ int rlb_conserved(rlb_solver *s, double out[5]);
  * pointer may be NULL.  Synchronises the stream. */
 int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t);
 
-/* Writes the raw populations, t, the flags and the configuration to a file
- * (host I/O; synchronises the stream). */
+/* Writes the raw populations (for AA in the layout of the current step's
+ * parity), t, the flags and the configuration to a file (host I/O;
+ * synchronises the stream). */
 int rlb_save(rlb_solver *s, const char *path);
 
 /* Restores a state written by rlb_save into a solver with the same
