@@ -112,3 +112,24 @@ def test_equilibrium_is_linear_in_n(lat):
     eq = Equilibrium(lat)
     a, b = eq(3 * n, T, U), 3 * eq(n, T, U)
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+
+
+def test_rest_equilibrium_positive_only_between_0745_and_220(lat):
+    """At rest the third-order equilibrium depends on a point only through
+    its shell energy, and it is positive on every shell only for
+    0.745 < T < 2.20 (a property of the four Laguerre energies and the
+    projection, the same for any weight vertex; the paper's remark that
+    large reference temperatures are unstable rests on it)."""
+    eq = Equilibrium(lat)
+    U = np.array([[1.0, 0, 0, 0]])
+    def min_ratio(T):
+        return float((eq(np.array([1.0]), np.array([T]), U)[0] / lat.w).min())
+    for T in (0.75, 1.0, 1.5, 2.2):
+        assert min_ratio(T) > 0, T
+    for T in (0.745, 2.21):
+        assert min_ratio(T) < 0, T
+    # the ratio depends on the shell only
+    f = eq(np.array([1.3]), np.array([0.9]), U)[0] / lat.w
+    for l in range(4):
+        r = f[lat.shell == l]
+        assert np.ptp(r) < 1e-13 * np.max(np.abs(r)), l
