@@ -279,12 +279,13 @@ void rlb_batch_destroy(rlb_batch *b);
  * (a shock tube or a periodic box, each with its own precision, relaxation,
  * step count and initial fields) are submitted at any time; the worker
  * admits them first-come-first-served as soon as their footprint fits in
- * the pool, and advances everything resident in rounds: each box by
- * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), each
- * tube by max(chunk_steps, chunk_steps * 4096 / nz) steps, all resident
- * tubes of one precision and model in one persistent launch.  Finished
- * requests are read back, their memory is freed and they are reported by
- * rlb_server_poll.  A request's result does not depend on what else is
+ * the pool.  Work runs on four streams (tubes of each precision, and two
+ * for boxes), each advancing on its own: when a stream has finished its last
+ * work, its finished requests are read back, freed and reported by
+ * rlb_server_poll, and its next work is issued: each of its boxes by
+ * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), or each
+ * of its tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all
+ * resident tubes of one precision and model in one persistent launch.  A request's result does not depend on what else is
  * resident (the kernels never mix requests).  Times are seconds since the
  * server was created. */
 #define RLB_REQ_TUBE 0 /* 1 x 1 x nz lattice (nx = ny = 1)                */
@@ -331,7 +332,8 @@ int rlb_server_submit(rlb_server *s, const rlb_request *req, int64_t *id);
  * the first one.  *count is the number returned. */
 int rlb_server_poll(rlb_server *s, rlb_completion *out, int32_t max, int32_t *count, int32_t wait_ms);
 
-/* Requests submitted and not yet reported, and rounds run so far. */
+/* Requests submitted and not yet reported, and the number of times work
+ * has been issued to a stream so far. */
 int rlb_server_pending(rlb_server *s, int64_t *pending, int64_t *rounds);
 
 /* Stops the worker (pending requests are dropped) and releases the

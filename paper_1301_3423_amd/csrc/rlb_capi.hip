@@ -1116,6 +1116,8 @@ struct rlb_server {
   int *h_order[SERVE_GROUPS] = {};
   std::vector<int> free_slots;
   hipStream_t streams[SERVE_STREAMS] = {};
+  hipEvent_t done_ev[SERVE_STREAMS] = {}; // recorded after each stream's last issued work
+  bool busy[SERVE_STREAMS] = {};          // that work may still be running
   int next_box_stream = 0;
   std::thread worker;
   std::mutex mu;
@@ -1176,7 +1178,6 @@ int admit(rlb_server *sv, ServeReq *q) {
   q->t_admit = sv->now();
   q->remaining = r.steps;
   if (r.kind == RLB_REQ_BOX) {
-    q->stream_idx = SERVE_TUBE_STREAMS + (sv->next_box_stream++ % SERVE_BOX_STREAMS);
     rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s, r.order, RLB_PATTERN_AB};
     int rc = rlb_create(&q->box, &cfg, sv->pool + q->off, q->bytes, sv->streams[q->stream_idx]);
     if (rc != RLB_OK) return rc;
@@ -1301,13 +1302,14 @@ int64_t tube_round_steps(const rlb_server *sv, const ServeReq *q) {
   return std::min<int64_t>(q->remaining, std::max<int64_t>(sv->chunk, budget));
 }
 
-int tubes_advance(rlb_server *sv, int prec, int order) {
+int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {
   // all resident tubes of this precision and model, one persistent launch
   std::vector<ServeReq *> tubes;
   for (ServeReq *q : sv->resident)
     if (q->r.kind == RLB_REQ_TUBE && q->r.precision == prec && norm_order(q->r.order) == order && q->remaining > 0)
       tubes.push_back(q);
   if (tubes.empty()) return RLB_OK;
+  issued = true;
   const int p = tube_group(prec, order);
   std::stable_sort(tubes.begin(), tubes.end(), [&](ServeReq *a, ServeReq *b) {
     return static_cast<double>(a->r.nz) * tube_round_steps(sv, a) >
@@ -1350,30 +1352,80 @@ int tubes_advance(rlb_server *sv, int prec, int order) {
   return RLB_OK;
 }
 
+// The stream a resident request's work runs on.
+int request_stream(const ServeReq *q) {
+  if (q->r.kind == RLB_REQ_TUBE) return tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
+  return q->stream_idx;
+}
+
+// The worker.  Each stream runs on its own: whenever a stream has finished
+// the work last issued to it, its finished requests are read back and
+// released, queued requests that go to it are admitted, and its next work
+// is issued (one persistent launch per tube group of its precision, or
+// `chunk` steps of each of its boxes).  No stream waits for another.
 void serve_loop(rlb_server *sv) {
   (void)hipSetDevice(sv->device);
   for (;;) {
-    // admission: first come, first served, as long as memory and slots allow
+    bool any_busy = false;
+    for (int i = 0; i < SERVE_STREAMS; ++i) {
+      if (sv->busy[i] && hipEventQuery(sv->done_ev[i]) == hipSuccess) sv->busy[i] = false;
+      any_busy = any_busy || sv->busy[i];
+    }
+    bool progressed = false;
+    // completions on idle streams
+    {
+      std::vector<ServeReq *> keep;
+      for (ServeReq *q : sv->resident) {
+        if (q->remaining > 0 || sv->busy[request_stream(q)]) {
+          keep.push_back(q);
+          continue;
+        }
+        unsigned flags = 0;
+        const int crc = complete(sv, q, flags);
+        finish(sv, q, crc, flags);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        release(sv, q);
+        progressed = true;
+      }
+      sv->resident.swap(keep);
+    }
+    // admission: first come, first served, while memory, slots and an idle
+    // stream for the request allow
     std::vector<ServeReq *> admitted;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->resident.empty(); });
+      if (sv->resident.empty() && !any_busy)
+        sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
       if (sv->stop) return;
       while (!sv->queue.empty()) {
         ServeReq *q = sv->queue.front();
-        if (q->r.kind == RLB_REQ_TUBE && sv->free_slots.empty()) break;
+        int st = -1;
+        if (q->r.kind == RLB_REQ_TUBE) {
+          st = tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
+          if (sv->busy[st] || sv->free_slots.empty()) break;
+        } else {
+          for (int b = 0; b < SERVE_BOX_STREAMS && st < 0; ++b) {
+            const int c = SERVE_TUBE_STREAMS + (sv->next_box_stream + b) % SERVE_BOX_STREAMS;
+            if (!sv->busy[c]) st = c;
+          }
+          if (st < 0) break;
+        }
         size_t off = 0;
         if (!sv->alloc->alloc(q->bytes, off)) break;
         q->off = off;
         if (q->r.kind == RLB_REQ_TUBE) {
           q->slot = sv->free_slots.back();
           sv->free_slots.pop_back();
+        } else {
+          q->stream_idx = st;
+          sv->next_box_stream = (st - SERVE_TUBE_STREAMS + 1) % SERVE_BOX_STREAMS;
         }
         sv->queue.pop_front();
         admitted.push_back(q);
       }
     }
     for (ServeReq *q : admitted) {
+      progressed = true;
       const int rc = admit(sv, q);
       if (rc != RLB_OK) {
         finish(sv, q, rc, 0);
@@ -1383,35 +1435,50 @@ void serve_loop(rlb_server *sv) {
       }
       sv->resident.push_back(q);
     }
-    if (sv->resident.empty()) continue;
-    // one round
-    int rc = RLB_OK;
-    for (int prec : {RLB_FP64, RLB_MIXED})
-      for (int order : {RLB_ORDER3, RLB_ORDER2})
-        if (rc == RLB_OK) rc = tubes_advance(sv, prec, order);
-    for (ServeReq *q : sv->resident) {
-      if (rc != RLB_OK) break;
-      if (q->r.kind != RLB_REQ_BOX || q->remaining == 0) continue;
-      const int64_t s = std::min<int64_t>(q->remaining, sv->chunk);
-      rc = box_advance(sv, q, s);
-      q->remaining -= s;
-    }
-    for (int i = 0; i < SERVE_STREAMS; ++i) (void)hipStreamSynchronize(sv->streams[i]);
-    sv->rounds += 1;
-    // completions
-    std::vector<ServeReq *> keep;
-    for (ServeReq *q : sv->resident) {
-      if (rc == RLB_OK && q->remaining > 0) {
-        keep.push_back(q);
+    // next work on every idle stream
+    for (int st = 0; st < SERVE_STREAMS; ++st) {
+      if (sv->busy[st]) continue;
+      int rc = RLB_OK;
+      bool issued = false;
+      if (st < SERVE_TUBE_STREAMS) {
+        const int prec = st == tube_stream(tube_group(RLB_FP64, RLB_ORDER3)) ? RLB_FP64 : RLB_MIXED;
+        for (int order : {RLB_ORDER3, RLB_ORDER2})
+          if (rc == RLB_OK) rc = tubes_advance(sv, prec, order, issued);
+      } else {
+        for (ServeReq *q : sv->resident) {
+          if (rc != RLB_OK) break;
+          if (q->r.kind != RLB_REQ_BOX || q->stream_idx != st || q->remaining == 0) continue;
+          const int64_t n = std::min<int64_t>(q->remaining, sv->chunk);
+          rc = box_advance(sv, q, n);
+          q->remaining -= n;
+          issued = true;
+        }
+      }
+      if (rc != RLB_OK) {
+        // a launch on this stream failed: end every request on it with the error
+        (void)hipStreamSynchronize(sv->streams[st]);
+        std::vector<ServeReq *> keep;
+        for (ServeReq *q : sv->resident) {
+          if (request_stream(q) != st) {
+            keep.push_back(q);
+            continue;
+          }
+          finish(sv, q, rc, 0);
+          std::lock_guard<std::mutex> lk(sv->mu);
+          release(sv, q);
+        }
+        sv->resident.swap(keep);
+        progressed = true;
         continue;
       }
-      unsigned flags = 0;
-      const int crc = rc != RLB_OK ? rc : complete(sv, q, flags);
-      finish(sv, q, crc, flags);
-      std::lock_guard<std::mutex> lk(sv->mu);
-      release(sv, q);
+      if (issued) {
+        if (hipEventRecord(sv->done_ev[st], sv->streams[st]) != hipSuccess) (void)hipStreamSynchronize(sv->streams[st]);
+        else sv->busy[st] = true;
+        sv->rounds += 1;
+        progressed = true;
+      }
     }
-    sv->resident.swap(keep);
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
 }
 
@@ -1464,6 +1531,7 @@ int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t
   }
   for (int i = 0; i < SERVE_STREAMS; ++i) {
     hipError_t e = hipStreamCreateWithFlags(&sv->streams[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->done_ev[i], hipEventDisableTiming);
     if (e != hipSuccess) {
       rlb_server_destroy(sv);
       return hip_fail(e, "rlb_server_create: streams");
@@ -1548,8 +1616,10 @@ void rlb_server_destroy(rlb_server *sv) {
     q->slot = -1;
     release(sv, q);
   }
-  for (int i = 0; i < SERVE_STREAMS; ++i)
+  for (int i = 0; i < SERVE_STREAMS; ++i) {
+    if (sv->done_ev[i]) (void)hipEventDestroy(sv->done_ev[i]);
     if (sv->streams[i]) (void)hipStreamDestroy(sv->streams[i]);
+  }
   for (int k = 0; k < SERVE_GROUPS; ++k) {
     if (sv->h_desc[k]) (void)hipHostFree(sv->h_desc[k]);
     if (sv->h_order[k]) (void)hipHostFree(sv->h_order[k]);
