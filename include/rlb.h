@@ -285,7 +285,9 @@ void rlb_batch_destroy(rlb_batch *b);
  * rlb_server_poll, and its next work is issued: each of its boxes by
  * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), or each
  * of its tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all
- * resident tubes of one precision and model in one persistent launch.  A request's result does not depend on what else is
+ * resident tubes of one precision and model in one persistent launch.
+ * The four streams should each have a hardware queue: a process that has
+ * other busy streams should raise GPU_MAX_HW_QUEUES (HIP's default is 4).  A request's result does not depend on what else is
  * resident (the kernels never mix requests).  Times are seconds since the
  * server was created. */
 #define RLB_REQ_TUBE 0 /* 1 x 1 x nz lattice (nx = ny = 1)                */
