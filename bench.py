@@ -23,8 +23,13 @@ import numpy as np
 # hardware queue of their own; HIP gives a process four by default, and
 # streams made earlier in the process (torch's, the box legs') would then
 # share queues with them (measured: serving p50 0.51 s instead of 0.30 s).
-# Read by the HIP runtime when it starts, so set before torch is imported.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# Read by the HIP runtime when it starts, so set before torch is imported
+# (raised to 8 unless the environment already asks for more).
+try:
+    _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+except ValueError:
+    _queues = 0
+os.environ["GPU_MAX_HW_QUEUES"] = str(max(_queues, 8))
 
 REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
