@@ -1290,10 +1290,11 @@ int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
   return rlb_step(q->box, steps);
 }
 
-// Steps a resident tube takes in one round: at least chunk, and as many as
-// fit in chunk * TUBE_ROUND_CELLS lattice updates, so short tubes finish in
-// few rounds while a round stays about as long as a box chunk.  (Measured on
-// the serving mix at 18.4 requests/s: 4096 gave p50/p99 0.79/4.7 s, 8192
+// Steps a resident tube takes per launch of its group: at least chunk, and
+// as many as fit in chunk * TUBE_ROUND_CELLS lattice updates, so short tubes
+// finish in few launches while a launch stays about as long as a box chunk.
+// (Measured on the serving mix at 18.4 requests/s, with all streams then
+// synchronised after every launch: 4096 gave p50/p99 0.79/4.7 s, 8192
 // 0.70/3.8-3.9 s, 16384 0.76/3.5 s with slower boxes.)
 constexpr int64_t TUBE_ROUND_CELLS = 8192;
 
