@@ -209,11 +209,14 @@ class Solver:
         check(lib().rlb_create(ctypes.byref(h), ctypes.byref(cfg), ctypes.c_void_p(self.buffer.data_ptr()),
                                nbytes, _stream_ptr(self.stream)))
         self._h = h
+        self._free = lib().rlb_destroy
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().rlb_destroy(h)
+        # the destroy function is kept on the object: at interpreter exit the
+        # module's globals may already be gone
+        h, free = getattr(self, "_h", None), getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
     # -- fields -------------------------------------------------------------
@@ -332,14 +335,15 @@ class Batch:
         check(lib().rlb_batch_create(ctypes.byref(h), arr, len(tubes), _prec(precision), self.order,
                                      ctypes.c_void_p(self.buffer.data_ptr()), nbytes, _stream_ptr(self.stream)))
         self._h = h
+        self._free = lib().rlb_batch_destroy
 
     def __len__(self):
         return len(self.tubes)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().rlb_batch_destroy(h)
+        h, free = getattr(self, "_h", None), getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
     def init_tube(self, j, n, eps, vx, vy, vz):
@@ -410,6 +414,7 @@ class Server:
         check(lib().rlb_server_create(ctypes.byref(h), ctypes.c_void_p(self.pool.data_ptr()), int(pool_bytes),
                                       int(chunk_steps), int(max_tubes)))
         self._h = h
+        self._free = lib().rlb_server_destroy
         self._live = {}      # id -> (request, inputs, outputs)
 
     def submit(self, kind, shape, precision, steps, fields, tau=None, eta_s=None, outputs=True, order=ORDER3):
@@ -449,9 +454,9 @@ class Server:
         return done
 
     def close(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().rlb_server_destroy(h)
+        h, free = getattr(self, "_h", None), getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
     def __del__(self):
