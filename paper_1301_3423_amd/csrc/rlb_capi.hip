@@ -1503,9 +1503,11 @@ int rlb_server_create(rlb_server **out, void *d_pool, size_t pool_bytes, int32_t
   const size_t table = SERVE_GROUPS * (align256(max_tubes * sizeof(rlb::TubeDesc)) + align256(max_tubes * sizeof(int))) +
                        align256(max_tubes * sizeof(unsigned));
   if (pool_bytes <= table) return fail(RLB_ENOMEM, "rlb_server_create: pool too small");
+  int dev = 0;
+  RLB_HIP(hipGetDevice(&dev));
   rlb_server *sv = new (std::nothrow) rlb_server();
   if (!sv) return fail(RLB_EINVAL, "rlb_server_create: out of host memory");
-  RLB_HIP(hipGetDevice(&sv->device));
+  sv->device = dev;
   sv->pool = static_cast<char *>(d_pool);
   sv->pool_bytes = pool_bytes;
   sv->chunk = chunk_steps;
