@@ -278,8 +278,11 @@ void rlb_batch_destroy(rlb_batch *b);
  * A server owns a worker thread and a caller-owned device pool.  Requests
  * (a shock tube or a periodic box, each with its own precision, relaxation,
  * step count and initial fields) are submitted at any time; the worker
- * admits them first-come-first-served as soon as their footprint fits in
- * the pool.  Work runs on four streams (tubes of each precision, and two
+ * admits them in arrival order as soon as their footprint fits in the pool
+ * and their stream is idle (a box goes to the box stream with the least
+ * work left); a request waiting for its stream lets later requests bound
+ * for idle streams pass, one waiting for memory holds back all behind it.
+ * Work runs on four streams (tubes of each precision, and two
  * for boxes), each advancing on its own: when a stream has finished its last
  * work, its finished requests are read back, freed and reported by
  * rlb_server_poll, and its next work is issued: each of its boxes by

@@ -1118,7 +1118,6 @@ struct rlb_server {
   hipStream_t streams[SERVE_STREAMS] = {};
   hipEvent_t done_ev[SERVE_STREAMS] = {}; // recorded after each stream's last issued work
   bool busy[SERVE_STREAMS] = {};          // that work may still be running
-  int next_box_stream = 0;
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -1353,6 +1352,12 @@ int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {
   return RLB_OK;
 }
 
+// Population bytes a box still has to stream (read and write) in `steps` steps.
+double box_bytes_left(const rlb_request &r, int64_t steps) {
+  return 2.0 * static_cast<double>(steps) * static_cast<double>(request_cells(r)) * q_of(norm_order(r.order)) *
+         static_cast<double>(elem_bytes(r.precision));
+}
+
 // The stream a resident request's work runs on.
 int request_stream(const ServeReq *q) {
   if (q->r.kind == RLB_REQ_TUBE) return tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
@@ -1390,26 +1395,41 @@ void serve_loop(rlb_server *sv) {
       }
       sv->resident.swap(keep);
     }
-    // admission: first come, first served, while memory, slots and an idle
-    // stream for the request allow
+    // admission in arrival order, while memory and tube slots allow.  A box
+    // goes to the box stream with the least work left (population bytes
+    // still to stream) and waits until that stream is idle; a request that
+    // waits for its stream lets later requests bound for idle streams pass,
+    // while one that does not fit in memory holds back all behind it.
+    // (Measured on the serving mix at 21.2 requests/s against filling
+    // whichever box stream was idle, in arrival order: p99 3.55 s instead of
+    // 3.7-4.4 s, p50 0.32 s against 0.32-0.34 s.)
     std::vector<ServeReq *> admitted;
+    double box_work[SERVE_BOX_STREAMS] = {};
+    for (ServeReq *q : sv->resident)
+      if (q->r.kind == RLB_REQ_BOX) box_work[q->stream_idx - SERVE_TUBE_STREAMS] += box_bytes_left(q->r, q->remaining);
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       if (sv->resident.empty() && !any_busy)
         sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
       if (sv->stop) return;
-      while (!sv->queue.empty()) {
-        ServeReq *q = sv->queue.front();
+      for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+        ServeReq *q = *it;
         int st = -1;
         if (q->r.kind == RLB_REQ_TUBE) {
           st = tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
-          if (sv->busy[st] || sv->free_slots.empty()) break;
+          if (sv->busy[st] || sv->free_slots.empty()) st = -1;
         } else {
-          for (int b = 0; b < SERVE_BOX_STREAMS && st < 0; ++b) {
-            const int c = SERVE_TUBE_STREAMS + (sv->next_box_stream + b) % SERVE_BOX_STREAMS;
-            if (!sv->busy[c]) st = c;
-          }
-          if (st < 0) break;
+          // the box stream with the least work left; the box waits for it
+          int best = 0;
+          for (int b = 1; b < SERVE_BOX_STREAMS; ++b)
+            if (box_work[b] < box_work[best] ||
+                (box_work[b] == box_work[best] && sv->busy[SERVE_TUBE_STREAMS + best] && !sv->busy[SERVE_TUBE_STREAMS + b]))
+              best = b;
+          if (!sv->busy[SERVE_TUBE_STREAMS + best]) st = SERVE_TUBE_STREAMS + best;
+        }
+        if (st < 0) { // waits for its stream: later requests for idle streams go first
+          ++it;
+          continue;
         }
         size_t off = 0;
         if (!sv->alloc->alloc(q->bytes, off)) break;
@@ -1419,9 +1439,9 @@ void serve_loop(rlb_server *sv) {
           sv->free_slots.pop_back();
         } else {
           q->stream_idx = st;
-          sv->next_box_stream = (st - SERVE_TUBE_STREAMS + 1) % SERVE_BOX_STREAMS;
+          box_work[st - SERVE_TUBE_STREAMS] += box_bytes_left(q->r, q->r.steps);
         }
-        sv->queue.pop_front();
+        it = sv->queue.erase(it);
         admitted.push_back(q);
       }
     }
