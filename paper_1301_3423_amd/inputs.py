@@ -11,6 +11,9 @@ random_box   smooth random flow: for each component (vx, vy, vz, theta)
              (redrawn when zero), amplitudes U(0.5, 1) and phases U(0, 2 pi);
              v is scaled so that max |v| = v_max exactly and
              T = 1 + 0.1 g_theta / max |g_theta|.
+boosted_box  random_box with a uniform velocity composed onto it
+             relativistically: a flow with net momentum, which a periodic
+             box keeps for ever.
 shock_tube   the Riemann problem of Sec. III: at rest, T = T_L for
              z < nz/2 and T_R otherwise.
 tube_batch   the parameters of many shock tubes: lengths, temperature
@@ -65,6 +68,22 @@ def random_box(nx, ny, nz, v_max, seed):
     n = T ** 3
     eps = 3.0 * T ** 4
     return n, eps, vx, vy, vz
+
+
+def boosted_box(nx, ny, nz, v_max, seed, boost):
+    """random_box(nx, ny, nz, v_max, seed) seen from a frame moving with the
+    uniform velocity -boost: each cell's velocity v becomes the relativistic
+    sum boost (+) v = [v / g + b + g/(1 + g) (b.v) b] / (1 + b.v), g the
+    Lorentz factor of b; n and eps (rest-frame scalars) are unchanged.
+    |boost| + v_max < 1 keeps every speed below 1 with margin."""
+    n, eps, vx, vy, vz = random_box(nx, ny, nz, v_max, seed)
+    b = np.asarray(boost, dtype=np.float64)
+    g = 1.0 / np.sqrt(1.0 - b @ b)
+    bv = b[0] * vx + b[1] * vy + b[2] * vz
+    c = g / (1.0 + g) * bv
+    den = 1.0 + bv
+    return (n, eps, (vx / g + b[0] + c * b[0]) / den, (vy / g + b[1] + c * b[1]) / den,
+            (vz / g + b[2] + c * b[2]) / den)
 
 
 def shock_tube(nz, T_left=1.0, T_right=0.8, nx=1, ny=1):

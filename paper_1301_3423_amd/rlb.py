@@ -92,6 +92,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("librlb.so is not built: run python -m paper_1301_3423_amd.build")
+        # torch ships its own HIP runtime under the same soname as the
+        # system's.  Imported first, it provides the one runtime the library
+        # then binds to; loading the library first would map the system's
+        # runtime beside torch's, and the second runtime to start finds no
+        # device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64
         L.rlb_lattice_info.argtypes = [i32, ctypes.POINTER(Lattice)]
@@ -177,6 +183,19 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(st.cuda_stream)
 
 
+def _order_buffer(buf, stream):
+    """torch's caching allocator orders a block's reuse after work on the
+    stream it was allocated on.  When the library runs on another stream,
+    wait for that stream's pending work (an earlier owner of the memory) and
+    record the library's stream on the block, so that it is not handed out
+    again while the library may still use it."""
+    import torch
+    cur = torch.cuda.current_stream(buf.device)
+    if stream != cur:
+        cur.synchronize()
+        buf.record_stream(stream)
+
+
 class Solver:
     """One periodic nx x ny x nz box on the current HIP device, third-order
     (order=3) or second-order (order=2) model, two population buffers
@@ -205,6 +224,7 @@ class Solver:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _order_buffer(self.buffer, self.stream)
         h = ctypes.c_void_p()
         check(lib().rlb_create(ctypes.byref(h), ctypes.byref(cfg), ctypes.c_void_p(self.buffer.data_ptr()),
                                nbytes, _stream_ptr(self.stream)))
@@ -331,6 +351,7 @@ class Batch:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _order_buffer(self.buffer, self.stream)
         h = ctypes.c_void_p()
         check(lib().rlb_batch_create(ctypes.byref(h), arr, len(tubes), _prec(precision), self.order,
                                      ctypes.c_void_p(self.buffer.data_ptr()), nbytes, _stream_ptr(self.stream)))
@@ -410,6 +431,9 @@ class Server:
         import torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        # the server writes the pool only on its own streams: let work still
+        # queued on torch's stream with an earlier owner of this memory finish
+        torch.cuda.current_stream(self.device).synchronize()
         h = ctypes.c_void_p()
         check(lib().rlb_server_create(ctypes.byref(h), ctypes.c_void_p(self.pool.data_ptr()), int(pool_bytes),
                                       int(chunk_steps), int(max_tubes)))

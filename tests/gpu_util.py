@@ -35,6 +35,25 @@ def field_errors(gpu, ref):
     for k in FIELDS:
         scale = uscale if k.startswith("U") else np.max(np.abs(r[k]))
         out[k] = float(np.max(np.abs(g[k] - r[k])) / scale)
+    comp = component_errors(gpu, ref)
+    note("  U errors, 4-vector scale / own scale: %s" % "  ".join(
+        "U%d %.2e / %.2e" % (j, out["U%d" % j], comp["U%d" % j]) for j in range(4)))
+    return out
+
+
+def component_errors(gpu, ref):
+    """The per-component form of the velocity error: max_x |U^j_gpu - U^j_ref|
+    / max_x |U^j_ref| for each j separately (infinite where the reference
+    component is zero everywhere).  Reported beside the 4-vector form; how
+    much of it plain rounding explains on the long runs is measured in
+    test_oracle_conditioning.py."""
+    g, r = split(gpu), split(ref)
+    out = {}
+    for j in range(4):
+        k = "U%d" % j
+        scale = np.max(np.abs(r[k]))
+        diff = np.max(np.abs(g[k] - r[k]))
+        out[k] = float(diff / scale) if scale > 0 else (0.0 if diff == 0 else float("inf"))
     return out
 
 
