@@ -182,6 +182,18 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
  * reduction order; synchronises the stream. */
 int rlb_conserved(rlb_solver *s, double out[5]);
 
+/* rlb_conserved for callers that cannot allocate device memory or lend
+ * the library a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same kernels, summation order and
+ * results as rlb_conserved, but the partial sums go to a fixed device array
+ * of the library (8 MiB per GPU, held until the process ends) instead of the
+ * solver's idle buffer or staging area, which stay untouched.  Allocates
+ * nothing.  Limits: at most 33,554,432 cells (2^25; e.g. 320^3), and no
+ * walls (their per-cell sums need a cells-sized array): RLB_EINVAL
+ * otherwise.  Synchronises the stream.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (from several threads) race. */
+int rlb_conserved_noalloc(rlb_solver *s, double out[5]);
+
 /* Sticky status flags (RLB_FLAG_*) and the current step count.  Either
  * pointer may be NULL.  Synchronises the stream. */
 int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t);

@@ -7,10 +7,27 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "rlb_kernels.hpp"
+
+// Scratch of rlb_conserved_noalloc: the Q partial sums of every block of
+// BLOCK * SUM_CELLS_PER_THREAD cells and the Q totals, for boxes of up to
+// NOALLOC_MAX_BLOCKS such blocks.  One copy per GPU, held until the process
+// ends (8 MiB); every call on a GPU shares it.
+namespace {
+constexpr int NOALLOC_MAX_BLOCKS = 8192;
+constexpr int64_t NOALLOC_MAX_CELLS =
+    static_cast<int64_t>(NOALLOC_MAX_BLOCKS) * rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
+constexpr size_t NOALLOC_DOUBLES = static_cast<size_t>(RLB_MAX_Q) * (NOALLOC_MAX_BLOCKS + 1);
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+} // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 namespace {
 
@@ -405,6 +422,72 @@ int rlb_read_fields(rlb_solver *s, double *n, double *eps, double *U4, double *P
 }
 
 namespace {
+int popsum_blocks(int64_t cells) {
+  const int64_t chunk = static_cast<int64_t>(rlb::BLOCK) * rlb::SUM_CELLS_PER_THREAD;
+  return static_cast<int>((cells + chunk - 1) / chunk);
+}
+
+// Box totals of N^0 and T^{0 nu} from the per-population totals (streaming
+// keeps each of them): k_popsum_partial writes Q * nblocks partial sums to
+// `partial`, k_popsum_final the Q totals after them, in a fixed order;
+// synchronises the stream.
+int conserved_popsum(rlb_solver *s, double *partial, double out[5]) {
+  const rlb::Geom g = geom_of(s);
+  const int nblocks = popsum_blocks(s->cells);
+  const int Q = q_of(s->cfg.order);
+  double *total = partial + static_cast<size_t>(Q) * nblocks;
+  const dim3 grid1(nblocks, Q), block(rlb::BLOCK);
+  if (s->cfg.precision == RLB_FP64)
+    hipLaunchKernelGGL(rlb::k_popsum_partial<double>, grid1, block, 0, s->stream,
+                       static_cast<const double *>(s->buf[s->cur]), g, partial, nblocks);
+  else
+    hipLaunchKernelGGL(rlb::k_popsum_partial<float>, grid1, block, 0, s->stream,
+                       static_cast<const float *>(s->buf[s->cur]), g, partial, nblocks);
+  hipLaunchKernelGGL(rlb::k_popsum_final, dim3(Q), block, 0, s->stream, partial, nblocks, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_popsum launch");
+  double tot[RLB_MAX_Q];
+  RLB_HIP(hipMemcpyAsync(tot, total, Q * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  RLB_HIP(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < 5; ++k) out[k] = 0.0;
+  // in the swapped AA state the values of population i sit in array inv(i)
+  const int swap = access_of(s) == rlb::AA_ODD ? 1 : 0;
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    for (int i = 0; i < M::Q; ++i) {
+      const rlb::Point &p = M::P[i];
+      const double pm[4] = {p.p0, p.p0 * p.tx * M::INV_R, p.p0 * p.ty * M::INV_R, p.p0 * p.tz * M::INV_R};
+      out[0] += p.p0 * tot[i ^ swap];
+      for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i ^ swap];
+    }
+    return 0;
+  });
+  return RLB_OK;
+}
+
+// Device address of the scratch array on device `dev`, looked up once per
+// device with that device current (each GPU holds its own copy of the
+// array; its host-side name is not a device address).
+int scratch_of_device(int dev, double **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RLB_EINVAL, "scratch: device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    RLB_HIP(hipGetDevice(&cur));
+    if (cur != dev) RLB_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(RLB_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double *>(g_scratch_ptr[dev]);
+  return RLB_OK;
+}
+} // namespace
+
+namespace {
 // Box totals with walls: per-cell N^0 and T^{0 nu} into the idle buffer,
 // then the fixed-order two-pass reduction over those five arrays.
 int conserved_walls(rlb_solver *s, double out[5]) {
@@ -442,39 +525,22 @@ int rlb_conserved(rlb_solver *s, double out[5]) {
   if (!s || !out) return fail(RLB_EINVAL, "rlb_conserved: NULL argument");
   if (!s->initialized) return fail(RLB_ESTATE, "rlb_conserved: call rlb_init_fields first");
   if (s->d_solid) return conserved_walls(s, out);
-  const rlb::Geom g = geom_of(s);
-  const int chunk = rlb::BLOCK * rlb::SUM_CELLS_PER_THREAD;
-  const int nblocks = static_cast<int>((s->cells + chunk - 1) / chunk);
-  const int Q = q_of(s->cfg.order);
-  double *partial = staging(s);
-  double *total = partial + static_cast<size_t>(Q) * nblocks;
-  const dim3 grid1(nblocks, Q), block(rlb::BLOCK);
-  if (s->cfg.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_popsum_partial<double>, grid1, block, 0, s->stream,
-                       static_cast<const double *>(s->buf[s->cur]), g, partial, nblocks);
-  else
-    hipLaunchKernelGGL(rlb::k_popsum_partial<float>, grid1, block, 0, s->stream,
-                       static_cast<const float *>(s->buf[s->cur]), g, partial, nblocks);
-  hipLaunchKernelGGL(rlb::k_popsum_final, dim3(Q), block, 0, s->stream, partial, nblocks, total);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "k_popsum launch");
-  double tot[RLB_MAX_Q];
-  RLB_HIP(hipMemcpyAsync(tot, total, Q * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-  RLB_HIP(hipStreamSynchronize(s->stream));
-  for (int k = 0; k < 5; ++k) out[k] = 0.0;
-  // in the swapped AA state the values of population i sit in array inv(i)
-  const int swap = access_of(s) == rlb::AA_ODD ? 1 : 0;
-  with_model(s->cfg.order, [&](auto m) {
-    using M = decltype(m);
-    for (int i = 0; i < M::Q; ++i) {
-      const rlb::Point &p = M::P[i];
-      const double pm[4] = {p.p0, p.p0 * p.tx * M::INV_R, p.p0 * p.ty * M::INV_R, p.p0 * p.tz * M::INV_R};
-      out[0] += p.p0 * tot[i ^ swap];
-      for (int mu = 0; mu < 4; ++mu) out[1 + mu] += p.p0 * pm[mu] * tot[i ^ swap];
-    }
-    return 0;
-  });
-  return RLB_OK;
+  return conserved_popsum(s, staging(s), out);
+}
+
+int rlb_conserved_noalloc(rlb_solver *s, double out[5]) {
+  if (!s || !out) return fail(RLB_EINVAL, "rlb_conserved_noalloc: NULL argument");
+  if (s->d_solid)
+    return fail(RLB_EINVAL, "rlb_conserved_noalloc: a box with walls needs per-cell sums; use rlb_conserved");
+  if (popsum_blocks(s->cells) > NOALLOC_MAX_BLOCKS)
+    return fail(RLB_EINVAL, "rlb_conserved_noalloc: " + std::to_string(s->cells) +
+                                " cells exceed the fixed scratch array (at most " +
+                                std::to_string(NOALLOC_MAX_CELLS) + " cells)");
+  if (!s->initialized) return fail(RLB_ESTATE, "rlb_conserved_noalloc: call rlb_init_fields first");
+  double *partial = nullptr;
+  const int rc = scratch_of_device(s->device, &partial);
+  if (rc != RLB_OK) return rc;
+  return conserved_popsum(s, partial, out);
 }
 
 int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t) {

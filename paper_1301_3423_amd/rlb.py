@@ -33,7 +33,7 @@ EXPORTS = ("rlb_lattice_info", "rlb_state_bytes", "rlb_create", "rlb_init_fields
            "rlb_batch_bytes", "rlb_batch_create", "rlb_batch_init", "rlb_batch_step", "rlb_batch_read",
            "rlb_batch_status", "rlb_batch_destroy", "rlb_request_bytes", "rlb_server_create",
            "rlb_server_submit", "rlb_server_poll", "rlb_server_pending", "rlb_server_destroy",
-           "rlb_walls_bytes", "rlb_set_walls", "rlb_strerror", "rlb_last_error")
+           "rlb_walls_bytes", "rlb_set_walls", "rlb_strerror", "rlb_last_error", "rlb_conserved_noalloc")
 REQ_TUBE, REQ_BOX = 0, 1
 
 
@@ -108,6 +108,7 @@ def lib():
         L.rlb_step.argtypes = [vp, i64]
         L.rlb_read_fields.argtypes = [vp, vp, vp, vp, vp, i32]
         L.rlb_conserved.argtypes = [vp, dp]
+        L.rlb_conserved_noalloc.argtypes = [vp, dp]
         L.rlb_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64)]
         L.rlb_save.argtypes = [vp, ctypes.c_char_p]
         L.rlb_load.argtypes = [vp, ctypes.c_char_p]
@@ -285,6 +286,13 @@ class Solver:
     def conserved(self):
         out = (ctypes.c_double * 5)()
         check(lib().rlb_conserved(self._h, out))
+        return np.array(out[:])
+
+    def conserved_noalloc(self):
+        """conserved() through rlb_conserved_noalloc (partial sums in the
+        library's fixed scratch array; no walls, at most 2^25 cells)."""
+        out = (ctypes.c_double * 5)()
+        check(lib().rlb_conserved_noalloc(self._h, out))
         return np.array(out[:])
 
     def status(self):

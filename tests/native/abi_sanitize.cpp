@@ -58,6 +58,14 @@ static int box(int order, int precision, int pattern, bool walls) {
   OK(rlb_step(s, 3));
   OK(rlb_conserved(s, c1));
   EXPECT(std::fabs(c1[0] - c0[0]) < 1e-6 * std::fabs(c0[0]));
+  if (!walls) {
+    double c2[5];
+    OK(rlb_conserved_noalloc(s, c2));
+    for (int k = 0; k < 5; ++k) EXPECT(c2[k] == c1[k]);
+  } else {
+    double c2[5];
+    EXPECT(rlb_conserved_noalloc(s, c2) == RLB_EINVAL);
+  }
   std::vector<double> n(C), eps(C), U(4 * C), P(C);
   OK(rlb_read_fields(s, n.data(), eps.data(), U.data(), P.data(), 0));
   uint32_t flags = 0;
