@@ -302,9 +302,44 @@ def run_tubes(precision, ntubes=512, steps=500, seed=4):
                 flags=flags, fields=fields)
 
 
-def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
+def latency_stats(lat):
+    lat = np.asarray(lat if len(lat) else [0.0])
+    return {"p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "count": int(len(lat))}
+
+
+def poisson_stream(sv, reqs, fields, rate, seed, label):
+    """Submits reqs at Poisson arrivals of `rate` per second to server sv and
+    waits for all of them; returns (completions in id order, makespan s)."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+    done = []
+    ids = []
+
+    def keep(cs):   # latency only: the output fields are dropped as they arrive
+        done.extend({k: v for k, v in c.items() if k != "fields"} for c in cs)
+
+    start = time.perf_counter()
+    for k, (r, f) in enumerate(zip(reqs, fields)):
+        while True:
+            now = time.perf_counter() - start
+            if now >= arrivals[k]:
+                break
+            keep(sv.poll(wait_ms=max(1, int(1000 * min(arrivals[k] - now, 0.05)))))
+        ids.append(sv.submit(r["kind"], r["shape"], r["precision"], r["steps"], f, eta_s=r["eta_s"], outputs=True))
+        if (k + 1) % 200 == 0:
+            print("bench: serving %s: %d submitted, %d done" % (label, k + 1, len(done)), file=sys.stderr, flush=True)
+    keep(sv.drain(timeout_s=900))
+    makespan = time.perf_counter() - start
+    by_id = {c["id"]: c for c in done}
+    return [by_id[i] for i in ids], makespan
+
+
+def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5, single_precision_requests=400):
     """Continuous batching under Poisson arrivals: capacity from a saturated
-    burst, then nreq requests at rate load * capacity."""
+    burst, then nreq requests at rate load * capacity; then the first
+    single_precision_requests requests of the same stream again at the same
+    rate, once all in float64 and once all in mixed precision."""
     import torch
     from paper_1301_3423_amd import inputs, rlb
     torch.cuda.empty_cache()
@@ -334,29 +369,15 @@ def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
     print("bench: serving capacity %.1f solves/s; Poisson rate %.1f/s" % (capacity, rate),
           file=sys.stderr, flush=True)
     # Poisson arrivals
-    rng = np.random.default_rng(seed + 1)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    done = []
-    start = time.perf_counter()
-    for k, (r, f) in enumerate(zip(reqs, fields)):
-        while True:
-            now = time.perf_counter() - start
-            if now >= arrivals[k]:
-                break
-            done.extend(sv.poll(wait_ms=max(1, int(1000 * min(arrivals[k] - now, 0.05)))))
-        submit(sv, r, f)
-        if (k + 1) % 200 == 0:
-            print("bench: serving: %d submitted, %d done" % (k + 1, len(done)), file=sys.stderr, flush=True)
-    done.extend(sv.drain(timeout_s=900))
-    makespan = time.perf_counter() - start
+    done, makespan = poisson_stream(sv, reqs, fields, rate, seed + 1, "mix")
     _, rounds = sv.pending()
     rounds -= rounds0
-    sv.close()
     lat = np.array([c["t_done"] - c["t_submit"] for c in done])
-    kinds = {}
-    for c, r in zip(sorted(done, key=lambda c: c["id"]), reqs):
+    kinds, precs = {}, {}
+    for c, r in zip(done, reqs):
         kinds.setdefault(r["kind"], []).append(c["t_done"] - c["t_submit"])
-    return {
+        precs.setdefault(r["precision"], []).append(c["t_done"] - c["t_submit"])
+    out = {
         "workload": "%d requests, Poisson arrivals at %.2f x measured capacity; 70%% tubes (N 200-8000, "
                     "100-2000 steps), 30%% boxes (32^3-128^3, |v|<=0.6, 200-1000 steps), eta/s U(0.01,0.5), "
                     "FP64/mixed 50/50" % (nreq, load),
@@ -368,9 +389,27 @@ def run_serving(nreq, load=0.7, chunk=50, pool_gib=48, seed=5):
         "p50_box_s": round(float(np.percentile(kinds.get("box", [0]), 50)), 4),
         "p99_tube_s": round(float(np.percentile(kinds.get("tube", [0]), 99)), 4),
         "p99_box_s": round(float(np.percentile(kinds.get("box", [0]), 99)), 4),
+        "by_precision": {p: latency_stats(v) for p, v in sorted(precs.items())},
         "flagged": int(sum(1 for c in done if c["flags"])), "errors": int(sum(1 for c in done if c["rc"])),
         "rounds": int(rounds), "chunk_steps": chunk, "completed": len(done),
     }
+    # the same requests, all in one precision, at the same arrival rate
+    m = min(single_precision_requests, nreq)
+    if m > 0:
+        single = {}
+        for prec in ("fp64", "mixed"):
+            rq = [dict(r, precision=prec) for r in reqs[:m]]
+            d, span = poisson_stream(sv, rq, fields[:m], rate, seed + 2, prec)
+            lat1 = [c["t_done"] - c["t_submit"] for c in d]
+            single[prec] = dict(latency_stats(lat1), solves_per_s=round(len(d) / span, 2),
+                                p99_tube_s=latency_stats([x for x, r in zip(lat1, rq) if r["kind"] == "tube"])["p99_s"],
+                                p99_box_s=latency_stats([x for x, r in zip(lat1, rq) if r["kind"] == "box"])["p99_s"],
+                                errors=int(sum(1 for c in d if c["rc"])))
+        out["single_precision_streams"] = dict(
+            workload="the first %d requests of the stream, all float64 or all mixed precision, Poisson arrivals "
+                     "at the same rate (%.2f/s, same arrival seed for both)" % (m, rate), **single)
+    sv.close()
+    return out
 
 
 def run_riemann():

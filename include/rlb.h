@@ -164,11 +164,17 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
 int rlb_init_fields(rlb_solver *s, const double *n, const double *eps, const double *vx,
                     const double *vy, const double *vz, int32_t on_device);
 
-/* Advances nsteps >= 0 time steps; asynchronous on the solver's stream.
+/* Advances nsteps >= 0 time steps of Eq. rlb:disc (Sec. II D): per cell
+ * the moments, the Landau-Lifshitz frame (Eq. eigenproblem, Eq.
+ * densitycal, eps = 3 n T), tau, the equilibrium (Eqs. coeff, disc1,
+ * equi3rd / equi2nd), the Anderson-Witting relaxation and the exact
+ * streaming by theta_i.  Asynchronous on the solver's stream.
  * RLB_ESTATE before rlb_init_fields, RLB_EHIP on a launch error. */
 int rlb_step(rlb_solver *s, int64_t nsteps);
 
-/* Macroscopic fields of the current (post-streaming, pre-collision) state:
+/* Macroscopic fields of the current (post-streaming, pre-collision) state,
+ * the quantities Sec. III reports: n = U_mu N^mu (Eq. densitycal), eps and
+ * U^mu from T^{mu nu} U_nu = eps U^mu (Eq. eigenproblem), P = eps / 3:
  * n, eps, P each nx*ny*nz values and U4 = 4*nx*ny*nz values laid out as
  * U^0 block, U^1 block, U^2 block, U^3 block.  Any output pointer may be
  * NULL.  on_device = 0: host arrays, the call synchronises the stream;
