@@ -304,9 +304,13 @@ void rlb_batch_destroy(rlb_batch *b);
  * for boxes), each advancing on its own: when a stream has finished its last
  * work, its finished requests are read back, freed and reported by
  * rlb_server_poll, and its next work is issued: each of its boxes by
- * `chunk_steps` steps (a replayed hipGraph of chunk_steps launches), or each
- * of its tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all
- * resident tubes of one precision and model in one persistent launch.
+ * chunk_steps * max(1, 262144 / cells) steps (replays of a hipGraph of
+ * chunk_steps launches; the last issue may end with fewer), or each of its
+ * tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all resident
+ * tubes of one precision and model in one persistent launch.  Tubes of 2048
+ * cells or more run as 1 x 1 x nz boxes (box kernels, which spread a step
+ * over many CUs, where a persistent tube launch gives a tube one CU), on
+ * the tube stream of their precision.
  * The four streams should each have a hardware queue: a process that has
  * other busy streams should raise GPU_MAX_HW_QUEUES (HIP's default is 4).  A request's result does not depend on what else is
  * resident (the kernels never mix requests).  Times are seconds since the

@@ -1152,6 +1152,15 @@ int64_t request_cells(const rlb_request &r) {
   return static_cast<int64_t>(r.nx) * r.ny * r.nz;
 }
 
+// Tubes of at least this many cells run as 1 x 1 x n boxes (still on the
+// tube stream of their precision): the box kernels spread a step over
+// n / 128 or n / 256 workgroups (many CUs), where the persistent tube launch
+// gives each tube one CU (about 8 MLUPS in float64, so a tube of 8000 cells
+// and 2000 steps would take 2 s).
+constexpr int32_t TUBE_AS_BOX_CELLS = 2048;
+
+bool runs_as_box(const rlb_request &r) { return r.kind == RLB_REQ_BOX || r.nz >= TUBE_AS_BOX_CELLS; }
+
 bool request_valid(const rlb_request &r, std::string &why) {
   if (r.kind != RLB_REQ_TUBE && r.kind != RLB_REQ_BOX) return why = "bad kind", false;
   if (r.kind == RLB_REQ_TUBE && (r.nx != 1 || r.ny != 1)) return why = "a tube needs nx = ny = 1", false;
@@ -1206,7 +1215,7 @@ namespace {
 size_t tube_pair_bytes(const rlb_request &r) { return 2 * tube_buffer_bytes(r.nz, r.precision, norm_order(r.order)); }
 
 size_t request_bytes_of(const rlb_request &r) {
-  if (r.kind == RLB_REQ_TUBE) return tube_pair_bytes(r);
+  if (!runs_as_box(r)) return tube_pair_bytes(r);
   return align256(rlb_state_bytes(r.nx, r.ny, r.nz, r.precision, r.order, RLB_PATTERN_AB));
 }
 
@@ -1242,7 +1251,7 @@ int admit(rlb_server *sv, ServeReq *q) {
   const double *f = q->fields.data();
   q->t_admit = sv->now();
   q->remaining = r.steps;
-  if (r.kind == RLB_REQ_BOX) {
+  if (runs_as_box(r)) {
     rlb_config cfg{r.nx, r.ny, r.nz, r.precision, r.tau_mode, r.tau, r.eta_s, r.order, RLB_PATTERN_AB};
     int rc = rlb_create(&q->box, &cfg, sv->pool + q->off, q->bytes, sv->streams[q->stream_idx]);
     if (rc != RLB_OK) return rc;
@@ -1288,7 +1297,7 @@ int admit(rlb_server *sv, ServeReq *q) {
 // Reads a finished request's fields into its host outputs; returns rc.
 int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
   const rlb_request &r = q->r;
-  if (r.kind == RLB_REQ_BOX) {
+  if (runs_as_box(r)) {
     int rc = rlb_read_fields(q->box, r.out_n, r.out_eps, r.out_U4, r.out_P, 0);
     if (rc != RLB_OK) return rc;
     return rlb_status(q->box, &flags, nullptr);
@@ -1330,29 +1339,42 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
   return RLB_OK;
 }
 
-// Advances one box by `steps`: full chunks replay a captured graph.
+// Advances one box by `steps`: each full chunk replays the box's captured
+// graph of `chunk` step launches, the rest is launched directly.
 int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
-  if (steps == sv->chunk) {
-    if (!q->graph_exec) {
-      hipStream_t st = sv->streams[q->stream_idx];
-      RLB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int64_t t_before = q->box->t;
-      const int cur_before = q->box->cur;
-      int rc = rlb_step(q->box, steps);
-      hipGraph_t gr = nullptr;
-      hipError_t e = hipStreamEndCapture(st, &gr);
-      q->box->t = t_before; // capture issued nothing: undo the host bookkeeping
-      q->box->cur = cur_before;
-      if (rc != RLB_OK) return rc;
-      if (e != hipSuccess) return hip_fail(e, "serve graph capture");
-      q->graph = gr;
-      RLB_HIP(hipGraphInstantiate(&q->graph_exec, gr, nullptr, nullptr, 0));
-    }
-    RLB_HIP(hipGraphLaunch(q->graph_exec, sv->streams[q->stream_idx]));
-    q->box->t += steps; // chunk is even: the current buffer is unchanged
-    return RLB_OK;
+  hipStream_t st = sv->streams[q->stream_idx];
+  int64_t full = steps / sv->chunk;
+  if (full > 0 && !q->graph_exec) {
+    RLB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int64_t t_before = q->box->t;
+    const int cur_before = q->box->cur;
+    int rc = rlb_step(q->box, sv->chunk);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &gr);
+    q->box->t = t_before; // capture issued nothing: undo the host bookkeeping
+    q->box->cur = cur_before;
+    if (rc != RLB_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "serve graph capture");
+    q->graph = gr;
+    RLB_HIP(hipGraphInstantiate(&q->graph_exec, gr, nullptr, nullptr, 0));
   }
-  return rlb_step(q->box, steps);
+  for (; full > 0; --full) {
+    RLB_HIP(hipGraphLaunch(q->graph_exec, st));
+    q->box->t += sv->chunk; // chunk is even: the current buffer is unchanged
+  }
+  return rlb_step(q->box, steps % sv->chunk);
+}
+
+// Steps a resident box takes per issue on its stream: `chunk` for boxes of
+// BOX_ROUND_CELLS cells or more, proportionally more (in whole chunks) for
+// smaller boxes and long tubes, so that every box streams about the same
+// bytes per issue and small requests are not held to the pace of large
+// ones.
+constexpr int64_t BOX_ROUND_CELLS = 262144; // 64^3
+
+int64_t box_round_steps(const rlb_server *sv, const ServeReq *q) {
+  const int64_t chunks = std::max<int64_t>(1, BOX_ROUND_CELLS / std::max<int64_t>(request_cells(q->r), 1));
+  return std::min<int64_t>(q->remaining, chunks * sv->chunk);
 }
 
 // Steps a resident tube takes per launch of its group: at least chunk, and
@@ -1372,7 +1394,7 @@ int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {
   // all resident tubes of this precision and model, one persistent launch
   std::vector<ServeReq *> tubes;
   for (ServeReq *q : sv->resident)
-    if (q->r.kind == RLB_REQ_TUBE && q->r.precision == prec && norm_order(q->r.order) == order && q->remaining > 0)
+    if (!runs_as_box(q->r) && q->r.precision == prec && norm_order(q->r.order) == order && q->remaining > 0)
       tubes.push_back(q);
   if (tubes.empty()) return RLB_OK;
   issued = true;
@@ -1425,10 +1447,7 @@ double box_bytes_left(const rlb_request &r, int64_t steps) {
 }
 
 // The stream a resident request's work runs on.
-int request_stream(const ServeReq *q) {
-  if (q->r.kind == RLB_REQ_TUBE) return tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
-  return q->stream_idx;
-}
+int request_stream(const ServeReq *q) { return q->stream_idx; }
 
 // The worker.  Each stream runs on its own: whenever a stream has finished
 // the work last issued to it, its finished requests are read back and
@@ -1483,7 +1502,7 @@ void serve_loop(rlb_server *sv) {
         int st = -1;
         if (q->r.kind == RLB_REQ_TUBE) {
           st = tube_stream(tube_group(q->r.precision, norm_order(q->r.order)));
-          if (sv->busy[st] || sv->free_slots.empty()) st = -1;
+          if (sv->busy[st] || (!runs_as_box(q->r) && sv->free_slots.empty())) st = -1;
         } else {
           // the box stream with the least work left; the box waits for it
           int best = 0;
@@ -1500,11 +1519,11 @@ void serve_loop(rlb_server *sv) {
         size_t off = 0;
         if (!sv->alloc->alloc(q->bytes, off)) break;
         q->off = off;
-        if (q->r.kind == RLB_REQ_TUBE) {
+        q->stream_idx = st;
+        if (!runs_as_box(q->r)) {
           q->slot = sv->free_slots.back();
           sv->free_slots.pop_back();
-        } else {
-          q->stream_idx = st;
+        } else if (q->r.kind == RLB_REQ_BOX) {
           box_work[st - SERVE_TUBE_STREAMS] += box_bytes_left(q->r, q->r.steps);
         }
         it = sv->queue.erase(it);
@@ -1531,15 +1550,15 @@ void serve_loop(rlb_server *sv) {
         const int prec = st == tube_stream(tube_group(RLB_FP64, RLB_ORDER3)) ? RLB_FP64 : RLB_MIXED;
         for (int order : {RLB_ORDER3, RLB_ORDER2})
           if (rc == RLB_OK) rc = tubes_advance(sv, prec, order, issued);
-      } else {
-        for (ServeReq *q : sv->resident) {
-          if (rc != RLB_OK) break;
-          if (q->r.kind != RLB_REQ_BOX || q->stream_idx != st || q->remaining == 0) continue;
-          const int64_t n = std::min<int64_t>(q->remaining, sv->chunk);
-          rc = box_advance(sv, q, n);
-          q->remaining -= n;
-          issued = true;
-        }
+      }
+      // boxes, and on the tube streams the long tubes that run as boxes
+      for (ServeReq *q : sv->resident) {
+        if (rc != RLB_OK) break;
+        if (!runs_as_box(q->r) || q->stream_idx != st || q->remaining == 0) continue;
+        const int64_t n = box_round_steps(sv, q);
+        rc = box_advance(sv, q, n);
+        q->remaining -= n;
+        issued = true;
       }
       if (rc != RLB_OK) {
         // a launch on this stream failed: end every request on it with the error

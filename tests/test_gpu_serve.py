@@ -19,6 +19,9 @@ MIX = [
     ("tube", (1, 1, 77), "mixed", 0, dict(eta_s=0.5), ("tube", 0.7)),
     ("box", (9, 8, 7), "mixed", 23, dict(eta_s=0.3), ("box", 0.5, 7)),
     ("tube", (1, 1, 1000), "fp64", 41, dict(eta_s=0.2), ("tube", 0.5)),
+    # long tubes run as boxes on the box streams
+    ("tube", (1, 1, 2500), "mixed", 37, dict(eta_s=0.1), ("tube", 0.6)),
+    ("tube", (1, 1, 3001), "fp64", 20, dict(eta_s=0.3), ("tube", 0.7)),
 ]
 
 
