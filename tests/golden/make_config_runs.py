@@ -8,7 +8,8 @@ half of numpy):
     python tests/golden/make_config_runs.py box64
     python tests/golden/make_config_runs.py boosted32
     python tests/golden/make_config_runs.py tubes
-    python tests/golden/make_config_runs.py merge
+    python tests/golden/make_config_runs.py tubes_alt    (after tubes)
+    python tests/golden/make_config_runs.py merge    (adds the parts written so far)
 
 Cases
   box64      the 128^3 float64 box workload (random fields |v| <= 0.5,
@@ -25,6 +26,13 @@ Cases
              (inputs.tube_batch(512, seed 4)) after 500 steps: the longest,
              the shortest, the longest of each eta/s, and the two tubes with
              the strongest shock at eta/s = 0.01 (which turn non-physical).
+  tubes_alt  the same unflagged tubes run again with the equilibrium taken
+             from the closed form printed in Appendix B (Eq. equi3rd, the
+             transcription in tests/appendix_equilibrium.py) instead of the
+             Table I projection: the same mathematics in another rounding
+             order.  The spread between the two float64 runs (tubeJ_spread:
+             max-norm relative differences of n, eps and U) measures how
+             closely float64 arithmetic fixes each tube's fields at all.
 Box fields are stored on a fixed seeded sample of cells (corners included)."""
 import os
 import sys
@@ -123,17 +131,59 @@ def run_tubes():
     return out
 
 
+def run_tubes_alt():
+    sys.path.insert(0, os.path.dirname(HERE))
+    from appendix_equilibrium import equi3rd
+    from oracle.equilibrium import Equilibrium
+
+    class ClosedForm(Equilibrium):
+        def __call__(self, n, T, U):
+            out = np.empty((len(n), self.lat.Q))
+            Uc = (U[:, 0], U[:, 1], U[:, 2], U[:, 3])
+            for i in range(self.lat.Q):
+                out[:, i] = equi3rd(n, T, Uc, tuple(self.lat.p[i]), self.lat.w[i])
+            return out
+
+    spec = inputs.tube_batch(512, 4)
+    part = os.path.join(HERE, "_part_tubes.npz")
+    with np.load(part if os.path.exists(part) else os.path.join(HERE, "oracle_config_runs.npz")) as ref:
+        out = {}
+        for j in tube_selection():
+            if int(ref["tube%d_flags" % j]):
+                continue
+            t = spec[j]
+            t0 = time.time()
+            o = rlb.Solver(1, 1, t["N"], lat=model_lattice(3), eta_s=t["eta_s"])
+            o.eq = ClosedForm(o.lat, 30)
+            o.init_fields(*inputs.shock_tube(t["N"], t["T_left"], t["T_right"]))
+            o.step(TUBE_STEPS)
+            r = o.read_fields()
+            spread = [float(np.max(np.abs(r[k] - ref["tube%d_%s" % (j, k)])) / np.max(np.abs(ref["tube%d_%s" % (j, k)])))
+                      for k in ("n", "eps", "U")]
+            out["tube%d_spread" % j] = np.array(spread)
+            print("tube %d closed-form spread n %.2e eps %.2e U %.2e (%.0f s)" % (j, *spread, time.time() - t0),
+                  flush=True)
+    return out
+
+
 def main(what):
     if what == "merge":
+        # the parts written so far, over what the merged file already holds
+        merged = os.path.join(HERE, "oracle_config_runs.npz")
         out = {}
-        for part in list(BOXES) + ["tubes"]:
-            with np.load(os.path.join(HERE, "_part_%s.npz" % part)) as z:
+        if os.path.exists(merged):
+            with np.load(merged) as z:
                 out.update({k: z[k] for k in z.files})
-        np.savez_compressed(os.path.join(HERE, "oracle_config_runs.npz"), **out)
-        for part in list(BOXES) + ["tubes"]:
-            os.remove(os.path.join(HERE, "_part_%s.npz" % part))
+        parts = [os.path.join(HERE, "_part_%s.npz" % p) for p in list(BOXES) + ["tubes", "tubes_alt"]]
+        parts = [p for p in parts if os.path.exists(p)]
+        for p in parts:
+            with np.load(p) as z:
+                out.update({k: z[k] for k in z.files})
+        np.savez_compressed(merged, **out)
+        for p in parts:
+            os.remove(p)
         return
-    out = run_tubes() if what == "tubes" else run_box(what)
+    out = run_tubes() if what == "tubes" else run_tubes_alt() if what == "tubes_alt" else run_box(what)
     np.savez(os.path.join(HERE, "_part_%s.npz" % what), **out)
 
 
