@@ -204,9 +204,10 @@ int rlb_conserved_noalloc(rlb_solver *s, double out[5]);
  * pointer may be NULL.  Synchronises the stream. */
 int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t);
 
-/* Writes the raw populations (for AA in the layout of the current step's
- * parity), t, the flags and the configuration to a file (host I/O;
- * synchronises the stream). */
+/* Writes the raw population buffer as the library stores it (tiles of
+ * 256 / element-size cells with 256-byte segments per population; for AA in
+ * the layout of the current step's parity), t, the flags and the
+ * configuration to a file (host I/O; synchronises the stream). */
 int rlb_save(rlb_solver *s, const char *path);
 
 /* Restores a state written by rlb_save into a solver with the same
@@ -254,7 +255,7 @@ int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes
  * between steps, launched longest-work-first.  Tubes never interact; a
  * failure (status flag) stays in its tube. */
 typedef struct rlb_tube {
-  int32_t n;        /* cells along z, >= 1                                  */
+  int32_t n;        /* cells along z, 1 .. 4,194,304 (2^22)                */
   int32_t tau_mode; /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */
   double tau;       /* when tau_mode == RLB_TAU_FIXED (> 1/2)               */
   double eta_s;     /* when tau_mode == RLB_TAU_ETA_S (> 0)                 */

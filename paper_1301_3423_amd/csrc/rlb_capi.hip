@@ -59,18 +59,19 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 // cell for host fields, which also holds the partial sums of rlb_conserved.
 size_t aa_stage_bytes(int64_t cells) { return align256(static_cast<size_t>(cells) * 7 * sizeof(double)); }
 
-// Elements between consecutive population arrays: the cell count rounded up
-// to 256 bytes, plus 256 bytes, so that the arrays do not all start at the
-// same offset modulo a large power of two.
-int64_t pop_stride(int64_t cells, int precision) {
-  const int64_t per = static_cast<int64_t>(PAD_BYTES / elem_bytes(precision));
-  return (cells + per - 1) / per * per + per;
-}
-
 // order 0 selects the default, the third-order model
 bool valid_order(int32_t o) { return o == 0 || o == RLB_ORDER2 || o == RLB_ORDER3; }
 int norm_order(int32_t o) { return o == 0 ? RLB_ORDER3 : o; }
 int q_of(int order) { return order == RLB_ORDER2 ? rlb::M2::Q : rlb::M3::Q; }
+
+// Bytes of one population buffer: whole tiles of 256 / elem_bytes cells,
+// each holding the Q populations of its cells in 256-byte segments (the
+// tiled storage of rlb_device.hpp); a multiple of 256.
+size_t pop_bytes(int64_t cells, int precision, int order) {
+  const int64_t tile = static_cast<int64_t>(PAD_BYTES / elem_bytes(precision));
+  const int64_t tiles = (cells + tile - 1) / tile;
+  return static_cast<size_t>(tiles) * q_of(norm_order(order)) * PAD_BYTES;
+}
 
 // Calls f with a value of the model type of `order` (normalised: 2 or 3).
 template <class F>
@@ -82,12 +83,14 @@ decltype(auto) with_model(int order, F &&f) {
 bool valid_dims(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   const int64_t c = static_cast<int64_t>(nx) * ny * nz;
-  // the two-lane kernels address (member offset + cell) * 8 bytes with
-  // 32-bit unsigned offsets, the member offset being at most one stride
-  // (<= cells + 64 elements): (2 cells + 64) * 8 < 2^32 for cells below
-  // 2^28 - 64; the cap keeps a margin
+  // cell indices, and the row starts the kernels form from them, stay
+  // within a signed 32-bit int with a margin
   return c <= (int64_t(1) << 28) - (int64_t(1) << 16);
 }
+
+// The one-lane row kernel (float32, rows of whole wavefronts) addresses the
+// x part of a tiled element with a 32-bit byte offset below nx * Q * 4.
+bool row_kernel_fits(int32_t nx) { return nx % 64 == 0 && static_cast<int64_t>(nx) * rlb::M3::Q * 4 < (int64_t(1) << 31); }
 
 } // namespace
 
@@ -98,7 +101,6 @@ struct rlb_solver {
   char *base;
   size_t bytes;
   int64_t cells;
-  int64_t stride;
   size_t buf_bytes; // one population buffer
   void *buf[2];
   unsigned *status;
@@ -121,7 +123,6 @@ rlb::Geom geom_of(const rlb_solver *s) {
   g.ny = s->cfg.ny;
   g.nz = s->cfg.nz;
   g.cells = static_cast<int>(s->cells);
-  g.stride = s->stride;
   return g;
 }
 
@@ -154,7 +155,7 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     rlb::k_step<M, double, WALLS, AC><<<grid, block, 0, s->stream>>>(
         static_cast<const double *>(in), static_cast<double *>(out), g, r, s->status, solid);
-  } else if (s->cfg.nx % 64 == 0) {
+  } else if (row_kernel_fits(s->cfg.nx)) {
     const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
     // rows of 64 cells: x is always wide, and the row kernel has one odd form
     constexpr int RAC = AC == rlb::AA_ODD_WIDE ? rlb::AA_ODD : AC;
@@ -170,11 +171,11 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
     if (s->nlinks > 0) {
       const dim3 grid(static_cast<unsigned>((s->nlinks + rlb::BLOCK - 1) / rlb::BLOCK)), block(rlb::BLOCK);
       if (s->cfg.precision == RLB_FP64)
-        rlb::k_bounce<double><<<grid, block, 0, s->stream>>>(static_cast<double *>(s->buf[1 - s->cur]), s->d_links,
-                                                             s->nlinks, s->stride);
+        rlb::k_bounce<M, double><<<grid, block, 0, s->stream>>>(static_cast<double *>(s->buf[1 - s->cur]),
+                                                                s->d_links, s->nlinks);
       else
-        rlb::k_bounce<float><<<grid, block, 0, s->stream>>>(static_cast<float *>(s->buf[1 - s->cur]), s->d_links,
-                                                            s->nlinks, s->stride);
+        rlb::k_bounce<M, float><<<grid, block, 0, s->stream>>>(static_cast<float *>(s->buf[1 - s->cur]),
+                                                               s->d_links, s->nlinks);
     }
   }
 }
@@ -273,8 +274,7 @@ size_t rlb_state_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t precision, in
   if (!valid_dims(nx, ny, nz) || (precision != RLB_FP64 && precision != RLB_MIXED) || !valid_order(order)) return 0;
   if (pattern != RLB_PATTERN_AB && pattern != RLB_PATTERN_AA) return 0;
   const int64_t cells = static_cast<int64_t>(nx) * ny * nz;
-  const size_t buf =
-      static_cast<size_t>(q_of(norm_order(order))) * pop_stride(cells, precision) * elem_bytes(precision);
+  const size_t buf = pop_bytes(cells, precision, order);
   if (pattern == RLB_PATTERN_AB) return 2 * buf + STATUS_BYTES;
   return buf + STATUS_BYTES + aa_stage_bytes(cells);
 }
@@ -310,8 +310,7 @@ int rlb_create(rlb_solver **out, const rlb_config *cfg, void *d_buf, size_t byte
   s->base = static_cast<char *>(d_buf);
   s->bytes = bytes;
   s->cells = static_cast<int64_t>(cfg->nx) * cfg->ny * cfg->nz;
-  s->stride = pop_stride(s->cells, cfg->precision);
-  s->buf_bytes = static_cast<size_t>(q_of(s->cfg.order)) * s->stride * elem_bytes(cfg->precision);
+  s->buf_bytes = pop_bytes(s->cells, cfg->precision, s->cfg.order);
   s->buf[0] = s->base;
   if (cfg->pattern == RLB_PATTERN_AA) {
     s->buf[1] = s->base; // one buffer
@@ -437,12 +436,16 @@ int conserved_popsum(rlb_solver *s, double *partial, double out[5]) {
   const int Q = q_of(s->cfg.order);
   double *total = partial + static_cast<size_t>(Q) * nblocks;
   const dim3 grid1(nblocks, Q), block(rlb::BLOCK);
-  if (s->cfg.precision == RLB_FP64)
-    hipLaunchKernelGGL(rlb::k_popsum_partial<double>, grid1, block, 0, s->stream,
-                       static_cast<const double *>(s->buf[s->cur]), g, partial, nblocks);
-  else
-    hipLaunchKernelGGL(rlb::k_popsum_partial<float>, grid1, block, 0, s->stream,
-                       static_cast<const float *>(s->buf[s->cur]), g, partial, nblocks);
+  with_model(s->cfg.order, [&](auto m) {
+    using M = decltype(m);
+    if (s->cfg.precision == RLB_FP64)
+      rlb::k_popsum_partial<M, double, true><<<grid1, block, 0, s->stream>>>(
+          static_cast<const double *>(s->buf[s->cur]), g, 0, partial, nblocks);
+    else
+      rlb::k_popsum_partial<M, float, true><<<grid1, block, 0, s->stream>>>(
+          static_cast<const float *>(s->buf[s->cur]), g, 0, partial, nblocks);
+    return 0;
+  });
   hipLaunchKernelGGL(rlb::k_popsum_final, dim3(Q), block, 0, s->stream, partial, nblocks, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_popsum launch");
@@ -508,10 +511,9 @@ int conserved_walls(rlb_solver *s, double out[5]) {
           static_cast<const float *>(s->buf[s->cur]), g, s->d_solid, cellv);
     return 0;
   });
-  rlb::Geom rows = g;
-  rows.stride = C; // five rows of C values
-  hipLaunchKernelGGL(rlb::k_popsum_partial<double>, dim3(nblocks, 5), dim3(rlb::BLOCK), 0, s->stream, cellv, rows,
-                     partial, nblocks);
+  // five plain rows of C values
+  rlb::k_popsum_partial<rlb::M3, double, false><<<dim3(nblocks, 5), dim3(rlb::BLOCK), 0, s->stream>>>(
+      cellv, g, C, partial, nblocks);
   hipLaunchKernelGGL(rlb::k_popsum_final, dim3(5), dim3(rlb::BLOCK), 0, s->stream, partial, nblocks, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "conserved (walls) launch");
@@ -556,9 +558,11 @@ int rlb_status(rlb_solver *s, uint32_t *flags, int64_t *t) {
 }
 
 namespace {
-// version 3: the configuration carries the model order, and the header the
-// hash of the solid mask (0 without walls)
-constexpr int32_t CKPT_VERSION = 3;
+// version 4: the populations are stored as the library holds them on the
+// device, in whole tiles (version 3 held one array per population); the
+// configuration carries the model order, the header the hash of the solid
+// mask (0 without walls)
+constexpr int32_t CKPT_VERSION = 4;
 struct CkptHeader {
   char magic[8];
   int32_t version;
@@ -588,10 +592,9 @@ int rlb_save(rlb_solver *s, const char *path) {
   int rc = rlb_status(s, &flags, nullptr);
   if (rc != RLB_OK) return rc;
   h.flags = flags;
-  const size_t eb = elem_bytes(s->cfg.precision);
-  std::vector<char> host(static_cast<size_t>(h.q) * s->cells * eb);
-  RLB_HIP(hipMemcpy2DAsync(host.data(), s->cells * eb, s->buf[s->cur], s->stride * eb, s->cells * eb, h.q,
-                           hipMemcpyDeviceToHost, s->stream));
+  // the population buffer as stored: whole tiles (rlb_device.hpp)
+  std::vector<char> host(s->buf_bytes);
+  RLB_HIP(hipMemcpyAsync(host.data(), s->buf[s->cur], s->buf_bytes, hipMemcpyDeviceToHost, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
   FILE *fp = std::fopen(path, "wb");
   if (!fp) return fail(RLB_EIO, std::string("rlb_save: cannot open ") + path);
@@ -622,13 +625,11 @@ int rlb_load(rlb_solver *s, const char *path) {
     std::fclose(fp);
     return fail(RLB_EINVAL, "rlb_load: checkpoint does not match this solver");
   }
-  const size_t eb = elem_bytes(s->cfg.precision);
-  std::vector<char> host(static_cast<size_t>(Q) * s->cells * eb);
+  std::vector<char> host(s->buf_bytes);
   const bool ok = std::fread(host.data(), 1, host.size(), fp) == host.size();
   std::fclose(fp);
   if (!ok) return fail(RLB_EIO, "rlb_load: short data");
-  RLB_HIP(hipMemcpy2DAsync(s->buf[s->cur], s->stride * eb, host.data(), s->cells * eb, s->cells * eb, Q,
-                           hipMemcpyHostToDevice, s->stream));
+  RLB_HIP(hipMemcpyAsync(s->buf[s->cur], host.data(), s->buf_bytes, hipMemcpyHostToDevice, s->stream));
   RLB_HIP(hipMemcpyAsync(s->status, &h.flags, sizeof(unsigned), hipMemcpyHostToDevice, s->stream));
   RLB_HIP(hipStreamSynchronize(s->stream));
   s->t = h.t;
@@ -767,8 +768,10 @@ struct rlb_batch {
 
 namespace {
 
+// A tube has at most 2^22 cells: the float32 tube kernel addresses its
+// tiled elements with 32-bit byte offsets (below n * Q * 4).
 bool valid_tube(const rlb_tube &tb) {
-  if (tb.n < 1 || tb.n > (1 << 27)) return false;
+  if (tb.n < 1 || tb.n > (1 << 22)) return false;
   if (tb.tau_mode == RLB_TAU_FIXED) return tb.tau > 0.5 && std::isfinite(tb.tau);
   if (tb.tau_mode == RLB_TAU_ETA_S) return tb.eta_s > 0.0 && std::isfinite(tb.eta_s);
   return false;
@@ -779,9 +782,7 @@ size_t batch_header_bytes(int ntubes) {
          align256(ntubes * sizeof(unsigned));
 }
 
-size_t tube_buffer_bytes(int32_t n, int precision, int order) {
-  return align256(static_cast<size_t>(q_of(order)) * pop_stride(n, precision) * elem_bytes(precision));
-}
+size_t tube_buffer_bytes(int32_t n, int precision, int order) { return pop_bytes(n, precision, order); }
 
 rlb::Geom tube_geom(const rlb_batch *b, int j) {
   rlb::Geom g;
@@ -789,7 +790,6 @@ rlb::Geom tube_geom(const rlb_batch *b, int j) {
   g.ny = 1;
   g.nz = b->tubes[j].n;
   g.cells = b->tubes[j].n;
-  g.stride = b->desc[j].stride;
   return g;
 }
 
@@ -867,7 +867,6 @@ int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int
     off += 2 * tb;
     d.steps = 0;
     d.n = tubes[j].n;
-    d.stride = static_cast<int32_t>(pop_stride(tubes[j].n, precision));
     d.cur = 0;
     d.mode = tubes[j].tau_mode == RLB_TAU_ETA_S ? 1 : 0;
     d.tau = tubes[j].tau;
@@ -1128,7 +1127,6 @@ struct ServeReq {
   int slot = -1;
   int cur = 0;
   int64_t tube_off[2] = {0, 0};
-  int32_t stride = 0;
 };
 
 // tubes are advanced per group of one precision and one model,
@@ -1261,7 +1259,6 @@ int admit(rlb_server *sv, ServeReq *q) {
   const size_t eb = elem_bytes(r.precision);
   const int order = norm_order(r.order);
   const size_t tb = tube_buffer_bytes(r.nz, r.precision, order);
-  q->stride = static_cast<int32_t>(pop_stride(r.nz, r.precision));
   q->tube_off[0] = static_cast<int64_t>(q->off / eb);
   q->tube_off[1] = static_cast<int64_t>((q->off + tb) / eb);
   q->cur = 0;
@@ -1274,7 +1271,6 @@ int admit(rlb_server *sv, ServeReq *q) {
   g.ny = 1;
   g.nz = r.nz;
   g.cells = r.nz;
-  g.stride = q->stride;
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
   with_model(order, [&](auto m) {
     using M = decltype(m);
@@ -1313,7 +1309,6 @@ int complete(rlb_server *sv, ServeReq *q, unsigned &flags) {
   g.ny = 1;
   g.nz = r.nz;
   g.cells = r.nz;
-  g.stride = q->stride;
   const dim3 grid(grid_of(C)), block(rlb::BLOCK);
   double *dn = stage, *de = stage + C, *dU = stage + 2 * C, *dP = stage + 6 * C;
   with_model(order, [&](auto m) {
@@ -1410,7 +1405,6 @@ int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {
     d.off[1] = q->tube_off[1];
     d.steps = tube_round_steps(sv, q);
     d.n = q->r.nz;
-    d.stride = q->stride;
     d.cur = q->cur;
     d.mode = q->r.tau_mode == RLB_TAU_ETA_S ? 1 : 0;
     d.tau = q->r.tau;

@@ -149,9 +149,40 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 struct Geom {
   int nx, ny, nz;
-  int cells;      // nx * ny * nz
-  int64_t stride; // elements between consecutive populations
+  int cells; // nx * ny * nz
 };
+
+// ---- storage of the populations: tiles --------------------------------------
+//
+// Populations are stored in tiles of TILE = 256 / sizeof(S) consecutive
+// cells (32 in float64, 64 in float32).  A tile holds population 0 of its
+// cells (256 bytes), then population 1, ..., population Q-1, so population i
+// of cell c is element
+//     (c / TILE) * Q * TILE + i * TILE + c % TILE
+// of a buffer.  A block of the step kernels then reads and writes a few
+// contiguous tiles instead of 128 separate arrays: measured on a load/store
+// probe with the step's access pattern at 256^3, 2.95 ms per step against
+// 3.24 ms with one array per population in float32, 6.25 ms against 7.0 ms
+// in float64.
+template <class S>
+inline constexpr int TILE = 256 / static_cast<int>(sizeof(S));
+
+// Element of population 0 of cell c >= 0 (population i adds i * TILE).
+template <class M, class S>
+__device__ __forceinline__ int64_t tile_elem(int c) {
+  constexpr unsigned T = TILE<S>;
+  const unsigned u = static_cast<unsigned>(c);
+  return static_cast<int64_t>(u / T) * (M::Q * T) + (u % T);
+}
+
+// The same for the x part of a cell inside a row that starts on a tile
+// boundary (nx a multiple of TILE): 32-bit, below nx * Q.
+template <class M, class S>
+__device__ __forceinline__ int tile_elem_x(int x) {
+  constexpr unsigned T = TILE<S>;
+  const unsigned u = static_cast<unsigned>(x);
+  return static_cast<int>((u / T) * (M::Q * T) + (u % T));
+}
 
 // (c - s) mod n for |s| <= MAXD; n is uniform across the wavefront.
 __device__ __forceinline__ int wrap_back(int c, int s, int n) {

@@ -1,9 +1,9 @@
-// Kernels of one periodic box.  One thread owns one cell; a block of 256
-// threads covers 256 consecutive cells in x-fastest order.
+// Kernels of one periodic box.  Cells are numbered x fastest; population i
+// of cell c lives at the tiled element (c / TILE) * Q * TILE + i * TILE +
+// c % TILE of a buffer (see tile_elem), written cur[i][c] below.
 //
-// Storage (per population i, x fastest, `stride` elements apart):
-//   the current buffer holds, for the current time t, values that land on
-//   cell x when streamed:  cur[i][x - theta_i] = f_i(x, t).
+// Storage: the current buffer holds, for the current time t, values that
+//   land on cell x when streamed:  cur[i][x - theta_i] = f_i(x, t).
 // So gathering cur[i][x - theta_i] yields the pre-collision state f(x, t)
 // (pull streaming, Eq. rlb:disc left side), and a step writes the
 // post-collision values of cell x to nxt[i][x], which is again of that
@@ -16,8 +16,8 @@ namespace rlb {
 
 inline constexpr int BLOCK = 256;
 
-// How a step reads and writes its populations (slot (i, x) = element
-// i * stride + x of a buffer):
+// How a step reads and writes its populations (slot (i, x) = population i
+// of cell x in a buffer):
 //   PULL     two buffers: gather cur[i][x - theta_i], store nxt[i][x];
 //   AA_EVEN  one buffer in its natural state, slot (i, x) = f_i(x): read
 //            slot (i, x), store the post-collision f_i to slot (inv(i), x);
@@ -79,6 +79,21 @@ __device__ __forceinline__ void store_plain(S *base, int cell, S v) {
   *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + boff) = v;
 }
 
+// Loads and stores at a 64-bit element index (tiled storage of boxes of
+// any size); the plain store is for the odd AA step, as store_plain.
+template <class S>
+__device__ __forceinline__ S load_e(const S *base, int64_t e) {
+  return base[e];
+}
+template <class S>
+__device__ __forceinline__ void store_e(S *base, int64_t e, S v) {
+  __builtin_nontemporal_store(v, base + e);
+}
+template <class S>
+__device__ __forceinline__ void store_e_plain(S *base, int64_t e, S v) {
+  base[e] = v;
+}
+
 __device__ __forceinline__ void cell_coords(int cell, const Geom &g, int &x, int &y, int &z) {
   x = cell % g.nx;
   const int yz = cell / g.nx;
@@ -91,15 +106,16 @@ __device__ __forceinline__ void cell_coords(int cell, const Geom &g, int &x, int
 template <class M, class S>
 __device__ __forceinline__ void gather(const S *__restrict__ cur, const Geom &g, const Shifts &sh,
                                        S (&f)[M::Q], int mode = PULL, int cell = 0) {
+  constexpr int T = TILE<S>;
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Point P = M::P[i];
     if (mode == AA_EVEN)
-      f[i] = load_at(cur + i * g.stride, cell);
+      f[i] = load_e(cur + i * T, tile_elem<M, S>(cell));
     else if (mode == AA_ODD)
-      f[i] = load_at(cur + (i ^ 1) * g.stride, sh.back<P.tx, P.ty, P.tz>());
+      f[i] = load_e(cur + (i ^ 1) * T, tile_elem<M, S>(sh.back<P.tx, P.ty, P.tz>()));
     else
-      f[i] = load_at(cur + i * g.stride, sh.back<P.tx, P.ty, P.tz>());
+      f[i] = load_e(cur + i * T, tile_elem<M, S>(sh.back<P.tx, P.ty, P.tz>()));
   });
 }
 
@@ -148,12 +164,12 @@ __device__ __forceinline__ void relax_cell(Get &&get, const Frame &fr, double ta
 // odd moments, the odd equilibrium coefficients and the velocity.  The 14
 // moments are summed across the two lanes (identical results in both), and
 // both lanes solve the same Landau problem.
-// Block sizes of the two-lane step kernels: 512 threads (256 cells) for the
-// third-order float64 kernel, whose LDS stash then fills 128 KB of the CU
-// (measured 1-2 % faster than 256 threads at 256^3), 256 threads (128
-// cells) otherwise.
+// Block size of the two-lane step kernels: 256 threads (128 cells).  Two
+// blocks share a CU (the third-order float64 stash takes 64 KB each), so
+// one block's arithmetic overlaps the other's loads (tiled storage, 256^3:
+// 6.55 ms per float64 step against 6.75 ms with one 512-thread block).
 template <class M, class S>
-inline constexpr int pair_block = (sizeof(S) == 8 && M::Q == 128) ? 512 : 256;
+inline constexpr int pair_block = 256;
 
 // (c - s) mod n for a shift s known only at run time, |s| <= MAXD.
 __device__ __forceinline__ int wrap_rt(int c, int s, int n) {
@@ -167,17 +183,16 @@ __device__ __forceinline__ int wrap_rt(int c, int s, int n) {
   return (c - s + (MAXD + 1) * n) % n;
 }
 
-// Per-lane gather offsets of the member m (sign sigma): offsets for the
-// source cell x - sigma*s along each axis, plus m * stride folded into z.
+// Per-lane gather offsets of the member with sign sigma: the source cell
+// x - sigma*s along each axis, as cell-index parts.
 struct HalfShifts {
   int xo[2 * MAXD + 1], yo[2 * MAXD + 1], zo[2 * MAXD + 1];
-  __device__ __forceinline__ HalfShifts(int x, int y, int z, int sigma, int m, const Geom &g) {
-    const int mstride = m * static_cast<int>(g.stride);
+  __device__ __forceinline__ HalfShifts(int x, int y, int z, int sigma, const Geom &g) {
 #pragma unroll
     for (int s = -MAXD; s <= MAXD; ++s) {
       xo[s + MAXD] = wrap_rt(x, sigma * s, g.nx);
       yo[s + MAXD] = wrap_rt(y, sigma * s, g.ny) * g.nx;
-      zo[s + MAXD] = wrap_rt(z, sigma * s, g.nz) * (g.nx * g.ny) + mstride;
+      zo[s + MAXD] = wrap_rt(z, sigma * s, g.nz) * (g.nx * g.ny);
     }
   }
   template <int TX, int TY, int TZ>
@@ -188,15 +203,11 @@ struct HalfShifts {
 
 __device__ __forceinline__ double add_partner(double v) { return v + __shfl_xor(v, 32); }
 
-// Block order of the row kernel: plain blockIdx.x.  The hardware deals
-// consecutive workgroups round-robin to the 8 XCDs, so at any time every XCD
-// works on neighbouring rows.  Giving each XCD its own contiguous eighth of
-// the lattice instead was measured 3-6 % slower (256^3); a row-kernel block
-// reads whole source rows, so it shares no cache line with other blocks.
 
 // Float64 populations of the last stash_n pairs of the third-order model
-// wait in LDS between the moment sums and the relaxation (256 B per thread,
-// 128 KB per 512-thread block), which keeps the live registers of the
+// wait in LDS between the moment sums and the relaxation (256 B per thread:
+// 64 KB per 256-thread step block, 128 KB per 512-thread tube workgroup),
+// which keeps the live registers of the
 // float64 kernels within two waves per SIMD.  The 33 pairs of the second-order model fit
 // in registers.
 template <class M, class S, int AC = PULL>
@@ -228,21 +239,23 @@ __device__ __forceinline__ void pair_cell_step(InPtr<S, AC> cur, OutPtr<S, AC> n
   if constexpr (WALLS) active = active && solid[cell] == 0;
   int x, y, z;
   cell_coords(cell, g, x, y, z);
+  constexpr int T = TILE<S>;
   S f[NPAIR];
   if constexpr (AC == AA_EVEN) {
     // own slot (2k + m, x)
-    const int own = m * static_cast<int>(g.stride) + cell;
+    const int64_t own = tile_elem<M, S>(cell) + m * T;
     static_for<0, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      f[k] = load_at(cur + (2 * k) * g.stride, own);
+      f[k] = load_e(cur + (2 * k) * T, own);
     });
   } else {
     // PULL: slot (2k + m, x - sigma theta); AA_ODD: slot (2k + 1 - m, x - sigma theta)
-    const HalfShifts sh(x, y, z, sigma, aa_odd(AC) ? 1 - m : m, g);
+    const HalfShifts sh(x, y, z, sigma, g);
+    const int mT = (aa_odd(AC) ? 1 - m : m) * T;
     static_for<0, NPAIR>([&](auto K) {
       constexpr int k = decltype(K)::value;
       constexpr Point P = M::P[2 * k];
-      f[k] = load_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>());
+      f[k] = load_e(cur + (2 * k) * T, tile_elem<M, S>(sh.back<P.tx, P.ty, P.tz>()) + mT);
     });
   }
   // moments of this lane's members; odd sums carry theta of point 2k
@@ -306,24 +319,23 @@ __device__ __forceinline__ void pair_cell_step(InPtr<S, AC> cur, OutPtr<S, AC> n
   // AA_ODD stores go to x + sigma theta: the offsets of x - (-sigma) theta;
   // AA_ODD_WIDE keeps only the y and z parts and wraps x per store
   struct NoShifts {
-    __device__ NoShifts(int, int, int, int, int, const Geom &) {}
+    __device__ NoShifts(int, int, int, int, const Geom &) {}
   };
   struct YZShifts {
     int yo[2 * MAXD + 1], zo[2 * MAXD + 1];
-    __device__ __forceinline__ YZShifts(int, int y, int z, int sigma, int m, const Geom &g) {
-      const int mstride = m * static_cast<int>(g.stride);
+    __device__ __forceinline__ YZShifts(int, int y, int z, int sigma, const Geom &g) {
 #pragma unroll
       for (int s = -MAXD; s <= MAXD; ++s) {
         yo[s + MAXD] = wrap_rt(y, sigma * s, g.ny) * g.nx;
-        zo[s + MAXD] = wrap_rt(z, sigma * s, g.nz) * (g.nx * g.ny) + mstride;
+        zo[s + MAXD] = wrap_rt(z, sigma * s, g.nz) * (g.nx * g.ny);
       }
     }
   };
   using Fwd = std::conditional_t<AC == AA_ODD, HalfShifts, std::conditional_t<AC == AA_ODD_WIDE, YZShifts, NoShifts>>;
-  const Fwd fwd(x, y, z, -sigma, m, g);
+  const Fwd fwd(x, y, z, -sigma, g);
   // PULL: slot (2k + m, x); AA_EVEN: slot (2k + 1 - m, x); AA_ODD: slot
   // (2k + m, x + sigma theta), whose offsets depend on the point
-  const int out_off = (AC == AA_EVEN ? 1 - m : m) * static_cast<int>(g.stride) + cell;
+  const int64_t out_off = tile_elem<M, S>(cell) + (AC == AA_EVEN ? 1 - m : m) * T;
   static_for<0, M::NSHELL>([&](auto L) {
     constexpr int l = decltype(L)::value;
     const ShellCoef<M, CT> s = shell_coefficients<M, l, CT>(e);
@@ -348,12 +360,13 @@ __device__ __forceinline__ void pair_cell_step(InPtr<S, AC> cur, OutPtr<S, AC> n
         // 13 wrapped values once and holding them through the arithmetic
         int xs = x;
         asm volatile("" : "+v"(xs));
-        const int off = fwd.zo[MAXD + P.tz] + fwd.yo[MAXD + P.ty] + wrap_fwd_wide(xs, sigma * P.tx, g.nx);
-        if (active) store_plain(nxt + (2 * k) * g.stride, off, S(fs));
+        const int dst = fwd.zo[MAXD + P.tz] + fwd.yo[MAXD + P.ty] + wrap_fwd_wide(xs, sigma * P.tx, g.nx);
+        if (active) store_e_plain(nxt + (2 * k) * T, tile_elem<M, S>(dst) + m * T, S(fs));
       } else if constexpr (AC == AA_ODD) {
-        if (active) store_plain(nxt + (2 * k) * g.stride, fwd.template back<P.tx, P.ty, P.tz>(), S(fs));
+        if (active)
+          store_e_plain(nxt + (2 * k) * T, tile_elem<M, S>(fwd.template back<P.tx, P.ty, P.tz>()) + m * T, S(fs));
       } else {
-        if (active) store_at(nxt + (2 * k) * g.stride, out_off, S(fs));
+        if (active) store_e(nxt + (2 * k) * T, out_off, S(fs));
       }
     });
   });
@@ -361,18 +374,17 @@ __device__ __forceinline__ void pair_cell_step(InPtr<S, AC> cur, OutPtr<S, AC> n
 }
 
 
-// Block order of the two-lane kernel: consecutive blocks (2k, 2k + 1) run
-// on one XCD.  Their cells are adjacent in x, so the cache lines at their
-// common edge (the x-shifted gathers reach 6 cells across it) are fetched
-// into one L2 instead of two: at 256^3 (two blocks per row) the float64
-// kernel's fetched bytes drop from 1.13x to 1.01x of the algorithmic reads.
-// Workgroups are dealt round-robin to the 8 XCDs, so physical block b runs
-// on XCD b % 8; the mapping is a bijection when the count is a multiple of
-// 16, and the identity otherwise.
+// Block order of the step kernels: each XCD takes a contiguous eighth of
+// the lattice.  The hardware deals workgroups round-robin to the 8 XCDs
+// (physical block b runs on XCD b % 8), so block b works on block
+// (b % 8) * nb / 8 + b / 8; the mapping is a bijection when the count is a
+// multiple of 8, and the identity otherwise.  With the tiled storage the
+// tiles an XCD reads and writes then lie together, and the shifted gathers
+// of neighbouring blocks meet in one L2 (256^3: mixed step 3.11 ms instead
+// of 3.17 ms in plain order, float64 6.46 instead of 6.64).
 __device__ __forceinline__ int pair_block_order(int b, int nb) {
-  if (nb % 16) return b;
-  const int xcd = b & 7, slot = b >> 3;
-  return 2 * (xcd + 8 * (slot >> 1)) + (slot & 1);
+  if (nb % 8) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
 template <class M, class S, bool WALLS, int AC = PULL>
@@ -400,24 +412,27 @@ struct TubeDesc {
   int64_t off[2]; // element offsets of the tube's two population buffers
   int64_t steps;  // steps to take in this launch
   int32_t n;      // cells along z
-  int32_t stride; // elements between consecutive populations
   int32_t cur;    // buffer holding the current state
   int32_t mode;   // 0 fixed tau, 1 tau from eta/s
+  int32_t pad;
   double tau, eta_s;
 };
 
 inline constexpr int TUBE_BLOCK = 512; // one workgroup fills a CU at two waves per SIMD
 
 // One tube cell per lane (float32): the cell index is z, so each lane keeps
-// the 13 wrapped z offsets and every population base is wavefront-uniform.
+// the tiled offsets of its 13 wrapped z and every population base is
+// wavefront-uniform (32-bit: a tube has at most 2^22 cells).
 template <class M, class S>
 __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__restrict__ out, const Geom &g,
                                                const Relax &rx, int z, unsigned &flags) {
+  constexpr int T = TILE<S>;
   const bool active = z < g.cells;
   const int zc = active ? z : g.cells - 1;
   int zo[2 * MAXD + 1];
 #pragma unroll
-  for (int s = -MAXD; s <= MAXD; ++s) zo[s + MAXD] = wrap_back(zc, s, g.nz);
+  for (int s = -MAXD; s <= MAXD; ++s) zo[s + MAXD] = static_cast<int>(tile_elem<M, S>(wrap_back(zc, s, g.nz)));
+  const int own = static_cast<int>(tile_elem<M, S>(zc));
   S f[M::Q];
   // loads at raised priority, as in the row kernel (batch of 512 tubes:
   // 4306 -> 4465 MLUPS)
@@ -425,7 +440,7 @@ __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__re
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Point P = M::P[i];
-    f[i] = load_at(in + i * g.stride, zo[P.tz + MAXD]);
+    f[i] = load_at(in + i * T, zo[P.tz + MAXD]);
   });
   __builtin_amdgcn_sched_barrier(0);
   __builtin_amdgcn_s_setprio(0);
@@ -435,7 +450,7 @@ __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__re
   const double tau = relaxation_time<M>(rx, fr.n, fr.T);
   relax_cell<M, S>([&](auto I) { return f[decltype(I)::value]; }, fr, tau, [&](auto I, S v) {
     constexpr int i = decltype(I)::value;
-    if (active) store_at(out + i * g.stride, zc, v);
+    if (active) store_at(out + i * T, own, v);
   });
   if (active) flags |= fl;
 }
@@ -454,7 +469,6 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
   g.ny = 1;
   g.nz = d.n;
   g.cells = d.n;
-  g.stride = d.stride;
   Relax rx;
   rx.mode = d.mode;
   rx.tau = d.tau;
@@ -496,52 +510,52 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
 // solid cells leave at once.
 // The odd AA step of the third-order model also keeps the 13 store offsets
 // of x + theta_i live through the relaxation; the last row_stash populations
-// then wait in LDS (16 KB per block), which keeps the kernel free of spills.
+// then wait in LDS (24 KB per block), which keeps the kernel free of spills.
 template <class M, class S, int AC>
-inline constexpr int row_stash = (AC == AA_ODD && M::Q == 128) ? 16 : 0;
+inline constexpr int row_stash = (AC == AA_ODD && M::Q == 128) ? 24 : 0;
 
 template <class M, class S, bool WALLS, int AC = PULL>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restrict__ status,
            const uint8_t *__restrict__ solid) {
-  const int blk = blockIdx.x;
+  const int blk = pair_block_order(blockIdx.x, gridDim.x);
   const int cell = blk * BLOCK + threadIdx.x;
   if (cell >= g.cells) return; // whole wavefronts only: cells is a multiple of 64
   if constexpr (WALLS) {
     if (solid[cell]) return;
   }
+  constexpr int T = TILE<S>;
   const int x = cell % g.nx;
   const int row = __builtin_amdgcn_readfirstlane(cell / g.nx);
   const int y = row % g.ny, z = row / g.ny;
-  const int64_t nxny = static_cast<int64_t>(g.nx) * g.ny;
-  const int64_t row0 = static_cast<int64_t>(row) * g.nx;
+  const int nxny = g.nx * g.ny;
+  // rows start on tile boundaries (nx % 64 == 0): a row starting at cell r
+  // starts at element r * Q, and the lanes only carry the tiled x parts
   int xo[2 * MAXD + 1];
-  int yo[2 * MAXD + 1], zo[2 * MAXD + 1]; // wavefront-uniform
+  int yo[2 * MAXD + 1], zo[2 * MAXD + 1]; // wavefront-uniform cell indices of row starts
 #pragma unroll
   for (int sft = -MAXD; sft <= MAXD; ++sft) {
-    xo[sft + MAXD] = wrap_back(x, sft, g.nx);
+    xo[sft + MAXD] = tile_elem_x<M, S>(wrap_back(x, sft, g.nx));
     yo[sft + MAXD] = wrap_back(y, sft, g.ny) * g.nx;
-    zo[sft + MAXD] = wrap_back(z, sft, g.nz) * static_cast<int>(nxny);
+    zo[sft + MAXD] = wrap_back(z, sft, g.nz) * nxny;
   }
+  const auto rowp = [&](int r) { return static_cast<int64_t>(r) * M::Q; };
   S f[M::Q];
-  const int own = static_cast<int>(row0) + x;
-  // a wavefront issuing its loads goes ahead of those busy with arithmetic,
-  // so the next cell's reads start sooner (measured at 256^3: 3.23-3.25 ms
-  // per step instead of 3.31-3.33; the same for the two-lane float64 kernel
-  // was 2 % slower, so it is not done there)
-  __builtin_amdgcn_s_setprio(3);
+  const int64_t own_row = rowp(row * g.nx);
+  const int own = tile_elem_x<M, S>(x);
+  // (loads at raised wave priority, which helped the untiled storage, made
+  // the tiled step about 1 % slower)
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr Point P = M::P[i];
     if constexpr (AC == AA_EVEN)
-      f[i] = load_at(cur + i * g.stride, own);
+      f[i] = load_at(cur + (i * T + own_row), own);
     else
-      f[i] = load_at(cur + ((AC == AA_ODD ? i ^ 1 : i) * g.stride + yo[P.ty + MAXD] + zo[P.tz + MAXD]),
+      f[i] = load_at(cur + ((AC == AA_ODD ? i ^ 1 : i) * T + rowp(yo[P.ty + MAXD] + zo[P.tz + MAXD])),
                      xo[P.tx + MAXD]);
   });
   // keep the phases apart: interleaving them raises the register peak
   __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_s_setprio(0);
   const Moments m = moments<M>(f);
   __builtin_amdgcn_sched_barrier(0);
   constexpr int RS = row_stash<M, S, AC>;
@@ -573,16 +587,16 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
     asm volatile("" : "+v"(xs));
     int xf[2 * MAXD + 1];
 #pragma unroll
-    for (int sft = -MAXD; sft <= MAXD; ++sft) xf[sft + MAXD] = wrap_back(xs, sft, g.nx);
+    for (int sft = -MAXD; sft <= MAXD; ++sft) xf[sft + MAXD] = tile_elem_x<M, S>(wrap_back(xs, sft, g.nx));
     relax_cell<M, S>(get, fr, tau, [&](auto I, S v) {
       constexpr int i = decltype(I)::value;
       constexpr Point P = M::P[i];
-      store_plain(nxt + (i * g.stride + yo[MAXD - P.ty] + zo[MAXD - P.tz]), xf[MAXD - P.tx], v);
+      store_plain(nxt + (i * T + rowp(yo[MAXD - P.ty] + zo[MAXD - P.tz])), xf[MAXD - P.tx], v);
     });
   } else {
     relax_cell<M, S>(get, fr, tau, [&](auto I, S v) {
       constexpr int i = decltype(I)::value;
-      store_at(nxt + (AC == AA_EVEN ? i ^ 1 : i) * g.stride, own, v);
+      store_at(nxt + ((AC == AA_EVEN ? i ^ 1 : i) * T + own_row), own, v);
     });
   }
   if (flags) atomicOr(status, flags);
@@ -619,12 +633,13 @@ __global__ void __launch_bounds__(BLOCK) k_init(const double *__restrict__ n_, c
       constexpr Point P = M::P[2 * k];
       CT E, O;
       shell_eval<M, 2 * k, CT>(s, E, O);
+      constexpr int T = TILE<S>;
       if (aa) {
-        store_at(cur + (2 * k) * g.stride, cell, S(P.w * (E + O)));
-        store_at(cur + (2 * k + 1) * g.stride, cell, S(P.w * (E - O)));
+        store_e(cur + (2 * k) * T, tile_elem<M, S>(cell), S(P.w * (E + O)));
+        store_e(cur + (2 * k + 1) * T, tile_elem<M, S>(cell), S(P.w * (E - O)));
       } else {
-        store_at(cur + (2 * k) * g.stride, sh.back<P.tx, P.ty, P.tz>(), S(P.w * (E + O)));
-        store_at(cur + (2 * k + 1) * g.stride, sh.back<-P.tx, -P.ty, -P.tz>(), S(P.w * (E - O)));
+        store_e(cur + (2 * k) * T, tile_elem<M, S>(sh.back<P.tx, P.ty, P.tz>()), S(P.w * (E + O)));
+        store_e(cur + (2 * k + 1) * T, tile_elem<M, S>(sh.back<-P.tx, -P.ty, -P.tz>()), S(P.w * (E - O)));
       }
     });
   });
@@ -683,13 +698,14 @@ struct Link {
   int32_t pop; // population i
 };
 
-template <class S>
+template <class M, class S>
 __global__ void __launch_bounds__(BLOCK) k_bounce(S *__restrict__ nxt, const Link *__restrict__ links,
-                                                  int64_t nlinks, int64_t stride) {
+                                                  int64_t nlinks) {
+  constexpr int T = TILE<S>;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
   if (k >= nlinks) return;
   const Link l = links[k];
-  nxt[l.pop * stride + l.dst] = nxt[(l.pop ^ 1) * stride + l.src];
+  nxt[l.pop * T + tile_elem<M, S>(l.dst)] = nxt[(l.pop ^ 1) * T + tile_elem<M, S>(l.src)];
 }
 
 // Per-cell N^0 and T^{0 nu} of the current state (zero at solid cells):
@@ -725,18 +741,20 @@ __global__ void __launch_bounds__(BLOCK) k_cell_conserved(const S *__restrict__ 
 // population the same way.
 inline constexpr int SUM_CELLS_PER_THREAD = 16;
 
-template <class S>
-__global__ void __launch_bounds__(BLOCK) k_popsum_partial(const S *__restrict__ cur, Geom g,
+// The values summed: population i of the tiled storage (TILED), or row i
+// of `cells` plain values `stride` apart.
+template <class M, class S, bool TILED>
+__global__ void __launch_bounds__(BLOCK) k_popsum_partial(const S *__restrict__ cur, Geom g, int64_t stride,
                                                           double *__restrict__ partial, int nblocks) {
   __shared__ double red[BLOCK];
   const int i = blockIdx.y;
-  const S *base = cur + i * g.stride;
+  const S *base = cur + (TILED ? static_cast<int64_t>(i) * TILE<S> : i * stride);
   const int chunk = BLOCK * SUM_CELLS_PER_THREAD;
   const int c0 = blockIdx.x * chunk;
   double acc = 0.0;
   for (int j = 0; j < SUM_CELLS_PER_THREAD; ++j) {
     const int c = c0 + j * BLOCK + threadIdx.x;
-    if (c < g.cells) acc += static_cast<double>(base[c]);
+    if (c < g.cells) acc += static_cast<double>(base[TILED ? tile_elem<M, S>(c) : c]);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
