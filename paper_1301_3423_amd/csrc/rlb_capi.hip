@@ -151,18 +151,19 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
   void *in = s->buf[s->cur];
   void *out = AC == rlb::PULL ? s->buf[1 - s->cur] : s->buf[s->cur];
   if (s->cfg.precision == RLB_FP64) {
-    constexpr int TB = rlb::pair_block<M, double>;
+    constexpr int TB = rlb::pair_block<M, double, AC>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     rlb::k_step<M, double, WALLS, AC><<<grid, block, 0, s->stream>>>(
         static_cast<const double *>(in), static_cast<double *>(out), g, r, s->status, solid);
   } else if (row_kernel_fits(s->cfg.nx)) {
-    const dim3 grid(grid_of(s->cells)), block(rlb::BLOCK);
     // rows of 64 cells: x is always wide, and the row kernel has one odd form
     constexpr int RAC = AC == rlb::AA_ODD_WIDE ? rlb::AA_ODD : AC;
+    constexpr int RB = rlb::step_block<RAC>;
+    const dim3 grid(static_cast<unsigned>((s->cells + RB - 1) / RB)), block(RB);
     rlb::k_step_row<M, float, WALLS, RAC><<<grid, block, 0, s->stream>>>(
         static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
   } else {
-    constexpr int TB = rlb::pair_block<M, float>;
+    constexpr int TB = rlb::pair_block<M, float, AC>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);
     rlb::k_step<M, float, WALLS, AC><<<grid, block, 0, s->stream>>>(
         static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);

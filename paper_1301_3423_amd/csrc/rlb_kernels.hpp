@@ -164,12 +164,18 @@ __device__ __forceinline__ void relax_cell(Get &&get, const Frame &fr, double ta
 // odd moments, the odd equilibrium coefficients and the velocity.  The 14
 // moments are summed across the two lanes (identical results in both), and
 // both lanes solve the same Landau problem.
-// Block size of the two-lane step kernels: 256 threads (128 cells).  Two
-// blocks share a CU (the third-order float64 stash takes 64 KB each), so
-// one block's arithmetic overlaps the other's loads (tiled storage, 256^3:
-// 6.55 ms per float64 step against 6.75 ms with one 512-thread block).
-template <class M, class S>
-inline constexpr int pair_block = 256;
+// Block sizes of the step kernels, for access AC.  Small blocks run in
+// different phases on one CU, so one block's arithmetic overlaps another's
+// loads: the pull steps use 128 threads (tiled storage, 256^3: float64
+// 6.24 ms against 6.31 ms with 64 threads, 6.44 ms with 256 and 6.75 ms with
+// 512; mixed 3.06 ms against 3.15 ms with 256).  The AA steps, whose even
+// step reads and writes only its own tiles, run best in 256-thread blocks
+// (even step 2.87 ms mixed and 5.86 ms float64 against 3.05 and 6.04 ms with
+// 64 threads).  The third-order float64 stash takes 256 B per thread.
+template <int AC>
+inline constexpr int step_block = AC == PULL ? 128 : 256;
+template <class M, class S, int AC = PULL>
+inline constexpr int pair_block = step_block<AC>;
 
 // (c - s) mod n for a shift s known only at run time, |s| <= MAXD.
 __device__ __forceinline__ int wrap_rt(int c, int s, int n) {
@@ -388,10 +394,10 @@ __device__ __forceinline__ int pair_block_order(int b, int nb) {
 }
 
 template <class M, class S, bool WALLS, int AC = PULL>
-__global__ void __launch_bounds__((pair_block<M, S>)) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((pair_block<M, S, AC>)) __attribute__((amdgpu_waves_per_eu(2)))
 k_step(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restrict__ status,
        const uint8_t *__restrict__ solid) {
-  constexpr int TB = pair_block<M, S>;
+  constexpr int TB = pair_block<M, S, AC>;
   __shared__ S lds[stash_rows<M, S, AC>][TB];
   const int blk = pair_block_order(blockIdx.x, gridDim.x);
   const int cell = blk * (TB / 2) + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
@@ -515,11 +521,12 @@ template <class M, class S, int AC>
 inline constexpr int row_stash = (AC == AA_ODD && M::Q == 128) ? 24 : 0;
 
 template <class M, class S, bool WALLS, int AC = PULL>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(step_block<AC>) __attribute__((amdgpu_waves_per_eu(2)))
 k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restrict__ status,
            const uint8_t *__restrict__ solid) {
+  constexpr int RB = step_block<AC>;
   const int blk = pair_block_order(blockIdx.x, gridDim.x);
-  const int cell = blk * BLOCK + threadIdx.x;
+  const int cell = blk * RB + threadIdx.x;
   if (cell >= g.cells) return; // whole wavefronts only: cells is a multiple of 64
   if constexpr (WALLS) {
     if (solid[cell]) return;
@@ -560,7 +567,7 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
   __builtin_amdgcn_sched_barrier(0);
   constexpr int RS = row_stash<M, S, AC>;
   constexpr int RS0 = M::Q - RS;
-  __shared__ S lds[RS > 0 ? RS : 1][BLOCK];
+  __shared__ S lds[RS > 0 ? RS : 1][RB];
   if constexpr (RS > 0) {
     static_for<RS0, M::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
