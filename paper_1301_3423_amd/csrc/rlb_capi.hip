@@ -156,12 +156,21 @@ void launch_step_kernels(rlb_solver *s, const rlb::Geom &g, const rlb::Relax &r)
     rlb::k_step<M, double, WALLS, AC><<<grid, block, 0, s->stream>>>(
         static_cast<const double *>(in), static_cast<double *>(out), g, r, s->status, solid);
   } else if (row_kernel_fits(s->cfg.nx)) {
-    // rows of 64 cells: x is always wide, and the row kernel has one odd form
-    constexpr int RAC = AC == rlb::AA_ODD_WIDE ? rlb::AA_ODD : AC;
-    constexpr int RB = rlb::step_block<RAC>;
+    // rows of 64 cells: x is always wide; the odd AA step rotates its stores
+    // through LDS when every block holds whole rows
+    constexpr int RB = rlb::step_block<AC>;
     const dim3 grid(static_cast<unsigned>((s->cells + RB - 1) / RB)), block(RB);
-    rlb::k_step_row<M, float, WALLS, RAC><<<grid, block, 0, s->stream>>>(
-        static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
+    if constexpr (rlb::aa_odd(AC)) {
+      if (RB % s->cfg.nx == 0)
+        rlb::k_step_row<M, float, WALLS, rlb::AA_ODD_ROT><<<grid, block, 0, s->stream>>>(
+            static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
+      else
+        rlb::k_step_row<M, float, WALLS, rlb::AA_ODD><<<grid, block, 0, s->stream>>>(
+            static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
+    } else {
+      rlb::k_step_row<M, float, WALLS, AC><<<grid, block, 0, s->stream>>>(
+          static_cast<const float *>(in), static_cast<float *>(out), g, r, s->status, solid);
+    }
   } else {
     constexpr int TB = rlb::pair_block<M, float, AC>;
     const dim3 grid(static_cast<unsigned>((s->cells + TB / 2 - 1) / (TB / 2))), block(TB);

@@ -29,9 +29,13 @@ inline constexpr int BLOCK = 256;
 // AA_ODD_WIDE is AA_ODD for boxes with nx > MAXD, where the two-lane kernel
 // computes the wrapped x of each store on the spot instead of keeping a
 // table of them live (which made the float64 kernel spill).
-enum Access { PULL = 0, AA_EVEN = 1, AA_ODD = 2, AA_ODD_WIDE = 3 };
+// AA_ODD_ROT is AA_ODD for the one-lane row kernel when every block holds
+// whole rows (nx divides the block size): the post-collision values are
+// first rotated along x through LDS, so that every wavefront stores whole,
+// aligned 256-byte segments instead of segments shifted by theta_x.
+enum Access { PULL = 0, AA_EVEN = 1, AA_ODD = 2, AA_ODD_WIDE = 3, AA_ODD_ROT = 4 };
 
-constexpr bool aa_odd(int ac) { return ac == AA_ODD || ac == AA_ODD_WIDE; }
+constexpr bool aa_odd(int ac) { return ac == AA_ODD || ac == AA_ODD_WIDE || ac == AA_ODD_ROT; }
 
 // (c + s) mod n for |s| <= MAXD < n.  Below zero c + s wraps to a huge
 // unsigned value, which min(t, t + n) replaces by t + n; at or above n,
@@ -518,7 +522,14 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
 // of x + theta_i live through the relaxation; the last row_stash populations
 // then wait in LDS (24 KB per block), which keeps the kernel free of spills.
 template <class M, class S, int AC>
-inline constexpr int row_stash = (AC == AA_ODD && M::Q == 128) ? 24 : 0;
+inline constexpr int row_stash = ((AC == AA_ODD || AC == AA_ODD_ROT) && M::Q == 128) ? 24 : 0;
+
+// Populations per LDS round of the rotated odd AA step (two buffers of
+// rot_batch x block floats, so one barrier per round): 8 rounds of 16 in
+// the third-order model, 3 of 22 in the second-order one.
+template <class M>
+inline constexpr int rot_batch = M::Q == 128 ? 16 : 22;
+static_assert(M3::Q % rot_batch<M3> == 0 && M2::Q % rot_batch<M2> == 0);
 
 template <class M, class S, bool WALLS, int AC = PULL>
 __global__ void __launch_bounds__(step_block<AC>) __attribute__((amdgpu_waves_per_eu(2)))
@@ -526,8 +537,15 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
            const uint8_t *__restrict__ solid) {
   constexpr int RB = step_block<AC>;
   const int blk = pair_block_order(blockIdx.x, gridDim.x);
-  const int cell = blk * RB + threadIdx.x;
-  if (cell >= g.cells) return; // whole wavefronts only: cells is a multiple of 64
+  int cell = blk * RB + threadIdx.x;
+  // the rotated odd step has workgroup barriers: wavefronts beyond the last
+  // cell stay, work on a copy of the last row and store nothing
+  const bool active = cell < g.cells;
+  if constexpr (AC == AA_ODD_ROT) {
+    if (!active) cell = g.cells - g.nx + (threadIdx.x & 63) % g.nx;
+  } else {
+    if (!active) return; // whole wavefronts only: cells is a multiple of 64
+  }
   if constexpr (WALLS) {
     if (solid[cell]) return;
   }
@@ -558,7 +576,7 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
     if constexpr (AC == AA_EVEN)
       f[i] = load_at(cur + (i * T + own_row), own);
     else
-      f[i] = load_at(cur + ((AC == AA_ODD ? i ^ 1 : i) * T + rowp(yo[P.ty + MAXD] + zo[P.tz + MAXD])),
+      f[i] = load_at(cur + ((aa_odd(AC) ? i ^ 1 : i) * T + rowp(yo[P.ty + MAXD] + zo[P.tz + MAXD])),
                      xo[P.tx + MAXD]);
   });
   // keep the phases apart: interleaving them raises the register peak
@@ -587,7 +605,39 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
   const unsigned flags = landau_frame(m, fr);
   const double tau = relaxation_time<M>(rx, fr.n, fr.T);
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (AC == AA_ODD) {
+  if constexpr (AC == AA_ODD_ROT) {
+    // stores to x + theta_i, rotated along the row through LDS: population i
+    // of this cell goes to LDS position (row start + (x + theta_x) mod nx);
+    // after the round's barrier each lane takes the value at its own
+    // position, which belongs to its own x in row (y + theta_y, z + theta_z),
+    // and stores it aligned.  Rows lie wholly in the block (RB % nx == 0).
+    constexpr int NB = rot_batch<M>;
+    __shared__ S stage[2][NB][RB];
+    const int rstart = static_cast<int>(threadIdx.x) - x; // block position of the row's first cell
+    int xs = x;
+    asm volatile("" : "+v"(xs));
+    int lp[2 * MAXD + 1]; // LDS position of x - sft
+#pragma unroll
+    for (int sft = -MAXD; sft <= MAXD; ++sft) lp[sft + MAXD] = rstart + wrap_back(xs, sft, g.nx);
+    relax_cell<M, S>(get, fr, tau, [&](auto I, S v) {
+      constexpr int i = decltype(I)::value;
+      constexpr Point P = M::P[i];
+      constexpr int buf = (i / NB) & 1;
+      if (active) stage[buf][i % NB][lp[MAXD - P.tx]] = v;
+      if constexpr (i % NB == NB - 1) {
+        // one barrier per round: a buffer is written again two rounds
+        // later, after every lane has passed the next round's barrier
+        __syncthreads();
+        static_for<0, NB>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          constexpr int q = i - (NB - 1) + j;
+          constexpr Point PQ = M::P[q];
+          const S w = stage[buf][j][threadIdx.x];
+          if (active) store_at(nxt + (q * T + rowp(yo[MAXD - PQ.ty] + zo[MAXD - PQ.tz])), own, w);
+        });
+      }
+    });
+  } else if constexpr (AC == AA_ODD) {
     // stores to x + theta_i; the x offsets are computed again here rather
     // than kept live through the arithmetic
     int xs = x;
@@ -606,7 +656,7 @@ k_step_row(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__re
       store_at(nxt + ((AC == AA_EVEN ? i ^ 1 : i) * T + own_row), own, v);
     });
   }
-  if (flags) atomicOr(status, flags);
+  if (active && flags) atomicOr(status, flags);
 }
 
 // Initial state: local equilibrium of (n, eps, v) in every cell, stored so

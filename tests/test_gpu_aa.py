@@ -24,8 +24,12 @@ SHAPES = [
     (13, 11, 7),     # ragged tail of the two-lane kernel
     (5, 4, 3),       # every axis below the largest displacement: wrap beyond the edge
     (9, 1, 17),      # a degenerate axis
-    (64, 3, 5),      # whole-wavefront rows (float32 one-lane kernel), small y and z
+    (64, 3, 5),      # whole-wavefront rows (float32 one-lane kernel), small y and z;
+                     # the odd step rotates its stores through LDS (four rows a block)
     (128, 12, 9),
+    (256, 2, 3),     # one row a block
+    (64, 1, 1),      # one row: the block's other wavefronts only join its barriers
+    (192, 2, 3),     # rows across blocks: the odd step stores at x + theta directly
 ]
 
 
