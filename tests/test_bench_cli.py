@@ -22,7 +22,9 @@ def test_kernel_names_and_profiles():
     assert bench.kernel_name(3, "fp64", 256) == "k_step<Model<3>, double, false, 0>"
     assert bench.kernel_name(3, "mixed", 100) == "k_step<Model<3>, float, false, 0>"
     assert bench.kernel_name(3, "fp64", 256, "aa_odd") == "k_step<Model<3>, double, false, 3>"
-    assert bench.kernel_name(3, "mixed", 256, "aa_odd") == "k_step_row<Model<3>, float, false, 2>"
+    # whole rows in a 256-cell block: stores rotated through LDS; else stored at x + theta
+    assert bench.kernel_name(3, "mixed", 256, "aa_odd") == "k_step_row<Model<3>, float, false, 4>"
+    assert bench.kernel_name(3, "mixed", 192, "aa_odd") == "k_step_row<Model<3>, float, false, 2>"
     assert bench.kernel_name(3, "fp64", 5, "aa_odd") == "k_step<Model<3>, double, false, 2>"
     # every committed summary names its kernel, sizes and the sources it was taken of
     prof = os.path.join(REPO, "profiles")
