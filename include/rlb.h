@@ -95,6 +95,9 @@ extern "C" {
 #define RLB_FLAG_NONFINITE 1u   /* a cell produced a NaN or infinity        */
 #define RLB_FLAG_NONPHYSICAL 2u /* n <= 0, eps <= 0 or |v| >= 1 in a cell   */
 #define RLB_FLAG_LANDAU 4u      /* the Landau-frame solve did not converge  */
+#define RLB_FLAG_STALL 8u       /* a tube kernel gave up waiting for its     */
+                                /* neighbouring work (never expected; the    */
+                                /* tube's results are then invalid)          */
 
 #define RLB_MAX_Q 128
 
@@ -251,9 +254,11 @@ int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes
  * 1 x 1 x n lattice on which only the z displacement of each point moves
  * anything.  A batch holds many tubes of one precision in one caller-owned
  * buffer and advances all of them in one persistent launch: one workgroup
- * per tube, each looping over that tube's steps with a workgroup barrier
- * between steps, launched longest-work-first.  Tubes never interact; a
- * failure (status flag) stays in its tube. */
+ * per tube, launched longest-work-first, whose wavefronts take the tube's
+ * (step, chunk) work in order and wait only for the neighbouring chunks'
+ * previous step (float64 tubes above 786,432 cells: a workgroup barrier
+ * between steps instead).  Tubes never interact; a failure (status flag)
+ * stays in its tube. */
 typedef struct rlb_tube {
   int32_t n;        /* cells along z, 1 .. 4,194,304 (2^22)                */
   int32_t tau_mode; /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */

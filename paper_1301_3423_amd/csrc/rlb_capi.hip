@@ -13,6 +13,10 @@
 
 #include "rlb_kernels.hpp"
 
+static_assert(rlb::FLAG_NONFINITE == RLB_FLAG_NONFINITE && rlb::FLAG_NONPHYSICAL == RLB_FLAG_NONPHYSICAL &&
+                  rlb::FLAG_LANDAU == RLB_FLAG_LANDAU && rlb::FLAG_TUBE_SYNC == RLB_FLAG_STALL,
+              "status flags of the kernels and of the C ABI must agree");
+
 // Scratch of rlb_conserved_noalloc: the Q partial sums of every block of
 // BLOCK * SUM_CELLS_PER_THREAD cells and the Q totals, for boxes of up to
 // NOALLOC_MAX_BLOCKS such blocks.  One copy per GPU, held until the process
@@ -787,6 +791,17 @@ bool valid_tube(const rlb_tube &tb) {
   return false;
 }
 
+// Chunks of one wavefront in the tube kernel, the most a workgroup's flags
+// hold, and the most (step, chunk) items one launch gives a tube.
+int64_t tube_chunks(int32_t n, int precision) {
+  const int ch = precision == RLB_FP64 ? rlb::TUBE_CHUNK<double> : rlb::TUBE_CHUNK<float>;
+  return (static_cast<int64_t>(n) + ch - 1) / ch;
+}
+int64_t tube_flow_chunks(int precision) {
+  return precision == RLB_FP64 ? rlb::TUBE_FLOW_CHUNKS<double> : rlb::TUBE_FLOW_CHUNKS<float>;
+}
+constexpr int64_t TUBE_ITEMS_MAX = (int64_t(1) << 31) - 1;
+
 size_t batch_header_bytes(int ntubes) {
   return align256(ntubes * sizeof(rlb::TubeDesc)) + align256(ntubes * sizeof(int)) +
          align256(ntubes * sizeof(unsigned));
@@ -961,42 +976,74 @@ int rlb_batch_step(rlb_batch *b, const int64_t *steps) {
     if (steps[j] > 0) ++active;
   }
   if (active == 0) return RLB_OK;
-  int rc = wait_staged(b);
-  if (rc != RLB_OK) return rc;
-  // longest work first (cells x steps), ties by index
-  std::vector<int> order;
-  order.reserve(active);
-  for (int j = 0; j < b->ntubes; ++j)
-    if (steps[j] > 0) order.push_back(j);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-    return static_cast<double>(b->tubes[a].n) * steps[a] > static_cast<double>(b->tubes[c].n) * steps[c];
-  });
-  for (int j = 0; j < b->ntubes; ++j) {
-    b->desc[j].steps = steps[j];
-    b->h_desc[j] = b->desc[j];
-  }
-  for (int k = 0; k < active; ++k) b->h_order[k] = order[k];
-  RLB_HIP(hipMemcpyAsync(b->d_desc, b->h_desc, b->ntubes * sizeof(rlb::TubeDesc), hipMemcpyHostToDevice, b->stream));
-  RLB_HIP(hipMemcpyAsync(b->d_order, b->h_order, active * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  RLB_HIP(hipEventRecord(b->staged, b->stream));
-  b->staged_pending = true;
-  const dim3 grid(active);
-  with_model(b->order, [&](auto m) {
-    using M = decltype(m);
-    if (b->precision == RLB_FP64)
-      rlb::k_tubes<M, double><<<grid, dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(
-          reinterpret_cast<double *>(b->pops), b->d_desc, b->d_order, b->d_status);
-    else
-      rlb::k_tubes<M, float><<<grid, dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(reinterpret_cast<float *>(b->pops),
-                                                                             b->d_desc, b->d_order, b->d_status);
-    return 0;
-  });
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "k_tubes launch");
-  for (int j = 0; j < b->ntubes; ++j) {
-    b->desc[j].cur ^= static_cast<int32_t>(steps[j] & 1);
-    b->desc[j].steps = 0;
-    b->t[j] += steps[j];
+  std::vector<int64_t> rem(steps, steps + b->ntubes);
+  // one launch per round: each tube takes as many of its remaining steps as
+  // keep its (step, chunk) items of the launch below 2^31 (a single round
+  // unless a run is very long)
+  for (;;) {
+    std::vector<int64_t> now(b->ntubes, 0);
+    std::vector<int> flow, sync;
+    for (int j = 0; j < b->ntubes; ++j) {
+      if (rem[j] == 0) continue;
+      const int64_t nch = tube_chunks(b->tubes[j].n, b->precision);
+      if (nch <= tube_flow_chunks(b->precision)) {
+        now[j] = std::min<int64_t>(rem[j], TUBE_ITEMS_MAX / nch);
+        flow.push_back(j);
+      } else {
+        now[j] = rem[j];
+        sync.push_back(j);
+      }
+    }
+    if (flow.empty() && sync.empty()) break;
+    int rc = wait_staged(b);
+    if (rc != RLB_OK) return rc;
+    // longest work first (cells x steps), ties by index
+    const auto longest = [&](int x, int y) {
+      return static_cast<double>(b->tubes[x].n) * now[x] > static_cast<double>(b->tubes[y].n) * now[y];
+    };
+    std::stable_sort(flow.begin(), flow.end(), longest);
+    std::stable_sort(sync.begin(), sync.end(), longest);
+    for (int j = 0; j < b->ntubes; ++j) {
+      b->desc[j].steps = now[j];
+      b->h_desc[j] = b->desc[j];
+    }
+    int k = 0;
+    for (int j : flow) b->h_order[k++] = j;
+    for (int j : sync) b->h_order[k++] = j;
+    RLB_HIP(hipMemcpyAsync(b->d_desc, b->h_desc, b->ntubes * sizeof(rlb::TubeDesc), hipMemcpyHostToDevice, b->stream));
+    RLB_HIP(hipMemcpyAsync(b->d_order, b->h_order, k * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    RLB_HIP(hipEventRecord(b->staged, b->stream));
+    b->staged_pending = true;
+    const int nf = static_cast<int>(flow.size()), ns = static_cast<int>(sync.size());
+    with_model(b->order, [&](auto m) {
+      using M = decltype(m);
+      if (b->precision == RLB_FP64) {
+        double *pops = reinterpret_cast<double *>(b->pops);
+        if (nf > 0)
+          rlb::k_tubes<M, double><<<dim3(nf), dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(pops, b->d_desc, b->d_order,
+                                                                                     b->d_status);
+        if (ns > 0)
+          rlb::k_tubes_sync<M, double><<<dim3(ns), dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(
+              pops, b->d_desc, b->d_order + nf, b->d_status);
+      } else {
+        float *pops = reinterpret_cast<float *>(b->pops);
+        if (nf > 0)
+          rlb::k_tubes<M, float><<<dim3(nf), dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(pops, b->d_desc, b->d_order,
+                                                                                    b->d_status);
+        if (ns > 0)
+          rlb::k_tubes_sync<M, float><<<dim3(ns), dim3(rlb::TUBE_BLOCK), 0, b->stream>>>(
+              pops, b->d_desc, b->d_order + nf, b->d_status);
+      }
+      return 0;
+    });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_tubes launch");
+    for (int j = 0; j < b->ntubes; ++j) {
+      b->desc[j].cur ^= static_cast<int32_t>(now[j] & 1);
+      b->desc[j].steps = 0;
+      b->t[j] += now[j];
+      rem[j] -= now[j];
+    }
   }
   return RLB_OK;
 }
@@ -1161,13 +1208,16 @@ int64_t request_cells(const rlb_request &r) {
 }
 
 // Tubes of at least this many cells run as 1 x 1 x n boxes (still on the
-// tube stream of their precision): the box kernels spread a step over
-// n / 128 or n / 256 workgroups (many CUs), where the persistent tube launch
-// gives each tube one CU (about 8 MLUPS in float64, so a tube of 8000 cells
-// and 2000 steps would take 2 s).
+// tube stream of their precision): the box kernels spread a step over n / 64
+// workgroups (many CUs), where the persistent tube launch gives each tube one
+// CU (about 8 MLUPS in float64, so a tube of 8000 cells and 2000 steps would
+// take 2 s).
 constexpr int32_t TUBE_AS_BOX_CELLS = 2048;
 
 bool runs_as_box(const rlb_request &r) { return r.kind == RLB_REQ_BOX || r.nz >= TUBE_AS_BOX_CELLS; }
+// the server's tubes always fit the dataflow form of the tube kernel
+static_assert(TUBE_AS_BOX_CELLS / rlb::TUBE_CHUNK<double> <= rlb::TUBE_FLOW_CHUNKS<double> &&
+              TUBE_AS_BOX_CELLS / rlb::TUBE_CHUNK<float> <= rlb::TUBE_FLOW_CHUNKS<float>);
 
 bool request_valid(const rlb_request &r, std::string &why) {
   if (r.kind != RLB_REQ_TUBE && r.kind != RLB_REQ_BOX) return why = "bad kind", false;
@@ -1392,7 +1442,9 @@ constexpr int64_t TUBE_ROUND_CELLS = 8192;
 
 int64_t tube_round_steps(const rlb_server *sv, const ServeReq *q) {
   const int64_t budget = static_cast<int64_t>(sv->chunk) * TUBE_ROUND_CELLS / std::max<int64_t>(q->r.nz, 1);
-  return std::min<int64_t>(q->remaining, std::max<int64_t>(sv->chunk, budget));
+  // the tube kernel counts a launch's (step, chunk) items in 32 bits
+  const int64_t cap = TUBE_ITEMS_MAX / tube_chunks(q->r.nz, q->r.precision);
+  return std::min<int64_t>(std::min<int64_t>(q->remaining, cap), std::max<int64_t>(sv->chunk, budget));
 }
 
 int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {

@@ -412,12 +412,9 @@ k_step(InPtr<S, AC> cur, OutPtr<S, AC> nxt, Geom g, Relax rx, unsigned *__restri
 
 // ---- many shock tubes in one persistent launch ----------------------------
 //
-// One workgroup per tube (taken from `order`, longest work first), looping
-// over that tube's steps; each step sweeps the tube in passes of TB/2 cells
-// and ends with a workgroup barrier, which also makes the step's stores
-// visible to the next step's gathers (all waves of a workgroup share one
-// CU and its caches).  Tubes are independent, so no workgroup ever waits on
-// another, and every workgroup leaves after its own step count.
+// One workgroup per tube (taken from `order`, longest work first) runs all
+// of that tube's steps.  Tubes are independent, so no workgroup ever waits
+// on another, and every workgroup leaves after its own step count.
 struct TubeDesc {
   int64_t off[2]; // element offsets of the tube's two population buffers
   int64_t steps;  // steps to take in this launch
@@ -429,6 +426,62 @@ struct TubeDesc {
 };
 
 inline constexpr int TUBE_BLOCK = 512; // one workgroup fills a CU at two waves per SIMD
+
+// Inside a workgroup the tube is cut into chunks of one wavefront (64 cells
+// in float32, one per lane; 32 in float64, two lanes per cell), and the
+// work is the sequence of (step s, chunk c) in the order k = s * nch + c.
+// Each wavefront takes the next k from a counter in LDS, waits until the
+// chunks its gathers reach (c - 1, c and c + 1 in the interior -- a gather
+// reaches at most 6 cells, less than a chunk -- see chunk_reach for the
+// periodic wrap) have finished step s - 1, computes the chunk and marks it
+// done.  Those chunks are the only ones that read the slots (c, s + 1)
+// overwrites (they read them as input of step s - 1) and the only ones whose
+// outputs (c, s) reads, so this is the whole dependence: there is no barrier
+// between steps, a wavefront that finishes its chunk goes on with the next
+// one, possibly of the next step, and neighbouring chunks are computed at
+// nearly the same time, so the cache lines they share are fetched once.
+// Every dependence of k is on smaller k, all of which were taken earlier,
+// so the work always progresses.  A step count per chunk is kept modulo
+// 256 (chunks in progress are at most a few steps apart).  Tubes with more
+// chunks than the flag array holds take the barrier form (k_tubes_sync).
+template <class S>
+inline constexpr int TUBE_CHUNK = sizeof(S) == 8 ? 32 : 64;
+// LDS flag bytes: float64 keeps 128 KB for its stash, float32 has no stash
+template <class S>
+inline constexpr int TUBE_FLOW_CHUNKS = sizeof(S) == 8 ? 24576 : 65536;
+// polls of a wait before it gives up and flags the tube (about 0.2 s; a
+// normal wait is a few microseconds); bounds every wait
+inline constexpr int TUBE_SPIN_LIMIT = 1 << 22;
+inline constexpr unsigned FLAG_TUBE_SYNC = 8u; // RLB_FLAG_STALL
+
+__device__ __forceinline__ bool step_reached(const volatile uint8_t *done, int c, uint8_t s) {
+  return static_cast<uint8_t>(done[c] - s) < 128u;
+}
+
+// The chunks whose cells the gathers of chunk c reach, cells
+// [c * CH - MAXD, end + MAXD) taken modulo n: a cyclic run of chunks from
+// `first`, `count` long.  Interior chunks need c - 1 .. c + 1; next to the
+// periodic wrap a last chunk shorter than MAXD cells makes the run reach
+// one chunk further; a tube shorter than that whole range needs every chunk.
+// The relation is symmetric, so the same chunks are the only ones that read
+// (as input of the previous step) the slots chunk c overwrites.
+template <int CH>
+__device__ __forceinline__ void chunk_reach(int c, int nch, int n, int &first, int &count) {
+  const int start = c * CH, end = start + CH < n ? start + CH : n;
+  if (end - start + 2 * MAXD >= n) {
+    first = 0;
+    count = nch;
+    return;
+  }
+  int lo = start - MAXD; // here n > 2 * MAXD: one wrap at most
+  if (lo < 0) lo += n;
+  int hi = end - 1 + MAXD;
+  if (hi >= n) hi -= n;
+  first = lo / CH;
+  // a run that wraps may come back into its first chunk
+  count = hi >= lo ? hi / CH - first + 1 : nch - first + hi / CH + 1;
+  if (count > nch) count = nch;
+}
 
 // One tube cell per lane (float32): the cell index is z, so each lane keeps
 // the tiled offsets of its 13 wrapped z and every population base is
@@ -465,13 +518,19 @@ __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__re
   if (active) flags |= fl;
 }
 
+// The tube's work in (step, chunk) order; `order` lists the workgroups'
+// tubes, each with at most TUBE_FLOW_CHUNKS<S> chunks and fewer than 2^31
+// (step, chunk) items in this launch (the host splits longer runs).
 template <class M, class S>
 __global__ void __launch_bounds__(TUBE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__restrict__ order,
         unsigned *__restrict__ status) {
   constexpr bool f64 = sizeof(S) == 8;
   constexpr int TB = TUBE_BLOCK;
+  constexpr int CH = TUBE_CHUNK<S>;
   __shared__ S lds[stash_rows<M, S>][f64 ? TB : 1];
+  __shared__ uint8_t done_[TUBE_FLOW_CHUNKS<S>];
+  __shared__ unsigned next_;
   const int j = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
   const TubeDesc d = desc[j]; // uniform: scalar loads
   Geom g;
@@ -483,20 +542,87 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
   rx.mode = d.mode;
   rx.tau = d.tau;
   rx.eta_s = d.eta_s;
-  // float64: two lanes per cell, TB/2 cells per pass; float32: one lane per
-  // cell, TB cells per pass
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  // float64: cell (lane & 31) of the wavefront's 32 on two lanes; float32:
+  // one cell per lane
+  const int slot = f64 ? (lane & 31) : lane;
+  unsigned flags = 0;
+  const unsigned nch = static_cast<unsigned>((d.n + CH - 1) / CH);
+  volatile uint8_t *done = done_;
+  for (unsigned c = threadIdx.x; c < nch; c += TB) done[c] = 0;
+  if (threadIdx.x == 0) next_ = 0;
+  __syncthreads();
+  const unsigned total = static_cast<unsigned>(d.steps) * nch;
+  for (;;) {
+    unsigned k = 0;
+    if (lane == 0) k = atomicAdd(&next_, 1u);
+    k = __builtin_amdgcn_readfirstlane(k);
+    if (k >= total) break;
+    const unsigned st = k / nch;
+    const unsigned c = k - st * nch;
+    int first, count;
+    chunk_reach<CH>(static_cast<int>(c), static_cast<int>(nch), d.n, first, count);
+    const uint8_t need = static_cast<uint8_t>(st);
+    int spins = 0;
+    for (;;) {
+      bool ready = true;
+      for (int q = 0, cq = first; q < count; ++q, cq = cq + 1 == static_cast<int>(nch) ? 0 : cq + 1)
+        ready = ready && step_reached(done, cq, need);
+      if (ready) break;
+      if (++spins >= TUBE_SPIN_LIMIT) {
+        flags |= FLAG_TUBE_SYNC; // never expected: give up the wait, keep going, report
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    // the neighbours' stores of step st - 1 are visible from here on
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int cur = (d.cur + static_cast<int>(st & 1u)) & 1;
+    const S *in = base + (cur ? d.off[1] : d.off[0]);
+    S *out = base + (cur ? d.off[0] : d.off[1]);
+    if constexpr (f64)
+      pair_cell_step<M, S, TB>(in, out, g, rx, static_cast<int>(c) * CH + slot, lds, flags);
+    else
+      tube_cell_step<M, S>(in, out, g, rx, static_cast<int>(c) * CH + slot, flags);
+    // this chunk's stores complete before it is marked done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) done[c] = static_cast<uint8_t>(st + 1);
+  }
+  if (flags) atomicOr(status + j, flags);
+}
+
+// Tubes beyond TUBE_FLOW_CHUNKS<S> chunks (float64 above 786,432 cells):
+// every step in passes of TB / 2 (float64) or TB (float32) cells, with a
+// workgroup barrier after each step (the step's stores are visible to the
+// next gathers: all wavefronts of a workgroup share one CU).
+template <class M, class S>
+__global__ void __launch_bounds__(TUBE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_tubes_sync(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__restrict__ order,
+             unsigned *__restrict__ status) {
+  constexpr bool f64 = sizeof(S) == 8;
+  constexpr int TB = TUBE_BLOCK;
+  __shared__ S lds[stash_rows<M, S>][f64 ? TB : 1];
+  const int j = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
+  const TubeDesc d = desc[j];
+  Geom g;
+  g.nx = 1;
+  g.ny = 1;
+  g.nz = d.n;
+  g.cells = d.n;
+  Relax rx;
+  rx.mode = d.mode;
+  rx.tau = d.tau;
+  rx.eta_s = d.eta_s;
   constexpr int per_pass = f64 ? TB / 2 : TB;
-  const int slot = f64 ? (threadIdx.x >> 6) * 32 + (threadIdx.x & 31) : static_cast<int>(threadIdx.x);
+  const int slot = f64 ? (static_cast<int>(threadIdx.x) >> 6) * 32 + (threadIdx.x & 31) : static_cast<int>(threadIdx.x);
+  const int wave0 = f64 ? (static_cast<int>(threadIdx.x) >> 6) * 32 : (static_cast<int>(threadIdx.x) & ~63);
   unsigned flags = 0;
   int cur = d.cur;
   for (int64_t st = 0; st < d.steps; ++st) {
     const S *in = base + (cur ? d.off[1] : d.off[0]);
     S *out = base + (cur ? d.off[0] : d.off[1]);
-    // the first cell of this wavefront in a pass (wavefront-uniform): waves
-    // whose cells all lie beyond the tube skip the pass
-    const int wave0 = f64 ? (static_cast<int>(threadIdx.x) >> 6) * 32 : (static_cast<int>(threadIdx.x) & ~63);
     for (int c0 = 0; c0 < d.n; c0 += per_pass) {
-      if (c0 + wave0 >= d.n) continue;
+      if (c0 + wave0 >= d.n) continue; // wavefronts wholly beyond the tube skip the pass
       if constexpr (f64)
         pair_cell_step<M, S, TB>(in, out, g, rx, c0 + slot, lds, flags);
       else

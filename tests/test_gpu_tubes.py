@@ -105,3 +105,51 @@ def test_failure_stays_in_its_tube():
     f1, _ = b.status(1)
     assert f0 == 0
     assert f1 & rlb.FLAG_NONPHYSICAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_many_chunks_and_steps_match_oracle(lat, precision):
+    """Tubes of many wavefront chunks (4000 cells: 63 chunks of 64 cells in
+    float32, 125 of 32 in float64) and a ragged one, advanced 60 steps in one
+    launch: the wavefronts work through (step, chunk) items in order, each
+    waiting only for its neighbouring chunks, across step boundaries."""
+    tubes = [dict(n=4000, eta_s=0.2), dict(n=1999, tau=0.85), dict(n=65, eta_s=0.05)]
+    fields = [inputs.shock_tube(4000, 1.0, 0.55), inputs.shock_tube(1999, 1.0, 0.7),
+              inputs.shock_tube(65, 1.0, 0.9)]
+    steps = [60, 45, 60]
+    b = rlb.Batch(tubes, precision=precision)
+    for j, f in enumerate(fields):
+        b.init_tube(j, *f)
+    note("batch %s: tubes %s, steps %s" % (precision, [t["n"] for t in tubes], steps))
+    b.step(steps)
+    for j, t in enumerate(tubes):
+        relax = {k: t[k] for k in ("tau", "eta_s") if k in t}
+        o = orlb.Solver(1, 1, t["n"], lat=lat, **relax)
+        o.init_fields(*fields[j])
+        o.step(steps[j])
+        err = field_errors(b.read_tube(j), o.read_fields())
+        flags, tt = b.status(j)
+        note("tube n=%d: max err %.2e flags %d" % (t["n"], max(err.values()), flags))
+        assert flags == 0 and tt == steps[j]
+        assert max(err.values()) <= TOL[precision], (t["n"], err)
+
+
+def test_tube_beyond_the_dataflow_flags_takes_the_barrier_kernel():
+    """A float64 tube of more chunks than a workgroup's flags hold (786,433
+    cells) runs in the barrier form of the kernel, in the same call as a
+    short tube that runs in the dataflow form; both equal the box path."""
+    n_big, n_small = 786433, 300
+    f_big = inputs.shock_tube(n_big, 1.0, 0.6)
+    f_small = inputs.shock_tube(n_small, 1.0, 0.8)
+    b = rlb.Batch([dict(n=n_big, eta_s=0.1), dict(n=n_small, eta_s=0.1)], precision="fp64")
+    b.init_tube(0, *f_big)
+    b.init_tube(1, *f_small)
+    note("batch fp64: a %d-cell tube (barrier kernel) and a %d-cell tube, 3 steps" % (n_big, n_small))
+    b.step(3)
+    for j, (n, f) in enumerate(((n_big, f_big), (n_small, f_small))):
+        s = rlb.Solver(1, 1, n, precision="fp64", eta_s=0.1)
+        s.init_fields(*f)
+        s.step(3)
+        err = field_errors(b.read_tube(j), s.read_fields())
+        assert b.status(j) == (0, 3)
+        assert max(err.values()) < 1e-13, (n, err)
