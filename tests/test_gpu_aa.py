@@ -30,6 +30,9 @@ SHAPES = [
     (256, 2, 3),     # one row a block
     (64, 1, 1),      # one row: the block's other wavefronts only join its barriers
     (192, 2, 3),     # rows across blocks: the odd step stores at x + theta directly
+    (96, 3, 4),      # float32 on the two-lane kernel with rows of whole wavefronts
+    (32, 5, 3),      # four rows a two-lane block
+    (32, 1, 1),      # one wavefront of cells in a block of four
 ]
 
 
