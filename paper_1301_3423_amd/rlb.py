@@ -24,7 +24,7 @@ FP64, MIXED = 0, 1
 TAU_FIXED, TAU_ETA_S = 0, 1
 ORDER3, ORDER2 = 3, 2
 PATTERN_AB, PATTERN_AA = 0, 1
-FLAG_NONFINITE, FLAG_NONPHYSICAL, FLAG_LANDAU = 1, 2, 4
+FLAG_NONFINITE, FLAG_NONPHYSICAL, FLAG_LANDAU, FLAG_STALL = 1, 2, 4, 8
 MAX_Q = 128
 
 # every symbol include/rlb.h declares

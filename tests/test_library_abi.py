@@ -21,6 +21,16 @@ def test_header_and_binding_agree():
     assert sorted(rlb.EXPORTS) == _declared()
 
 
+def test_header_constants_match_the_binding():
+    """Every #define RLB_<NAME> value of include/rlb.h equals the binding's <NAME>."""
+    src = open(os.path.join(REPO, "include", "rlb.h")).read()
+    found = dict(re.findall(r"#define RLB_([A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src))
+    found.pop("H", None)
+    assert len(found) >= 20
+    for name, value in found.items():
+        assert getattr(rlb, name) == int(value), name
+
+
 def test_library_exports_every_declared_symbol():
     L = rlb.lib()
     for name in _declared():
