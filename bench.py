@@ -124,26 +124,27 @@ def copy_calibration():
 # ---- rocprofv3 summaries (profiles/*.txt) ---------------------------------
 #
 # The commands below are run from /tmp with TMPDIR=/tmp on the GPU ($R is the
-# repository root); `python bench.py --summarize-profiles $R/gpurun_out/prof`
-# then reads their CSV output and writes one summary per kernel.
+# repository root, $OUT an output directory); `python bench.py
+# --summarize-profiles $OUT` then reads their CSV output and writes one
+# summary per kernel.
 _BOX_FLAGS = "--no-cpu --no-tubes --no-largest --no-configs --serve-requests 0"
 _TUBE_FLAGS = "--no-fp64 --no-second-order --no-walls --no-aa --no-configs --serve-requests 0 --no-cpu"
 PROFILE_RUNS = {
-    "trace": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof/trace -o run -- "
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d $OUT/trace -o run -- "
              "python3 $R/bench.py --steps 20 --warmup 2 " + _BOX_FLAGS,
-    "pmc_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/prof/pmc_fetch -o run -- "
+    "pmc_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $OUT/pmc_fetch -o run -- "
                  "python3 $R/bench.py --steps 3 --warmup 1 " + _BOX_FLAGS,
-    "pmc_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/prof/pmc_write -o run -- "
+    "pmc_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $OUT/pmc_write -o run -- "
                  "python3 $R/bench.py --steps 3 --warmup 1 " + _BOX_FLAGS,
-    "trace_tubes": "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/prof/trace_tubes -o run -- "
+    "trace_tubes": "rocprofv3 --kernel-trace --stats -f csv -d $OUT/trace_tubes -o run -- "
                    "python3 $R/bench.py --steps 2 --warmup 1 " + _TUBE_FLAGS,
-    "pmc_tubes_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/prof/pmc_tubes_fetch -o run -- "
+    "pmc_tubes_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $OUT/pmc_tubes_fetch -o run -- "
                        "python3 $R/bench.py --steps 2 --warmup 1 " + _TUBE_FLAGS,
-    "pmc_tubes_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/prof/pmc_tubes_write -o run -- "
+    "pmc_tubes_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $OUT/pmc_tubes_write -o run -- "
                        "python3 $R/bench.py --steps 2 --warmup 1 " + _TUBE_FLAGS,
-    "pmc_copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/prof/pmc_copy_fetch -o run -- "
+    "pmc_copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d $OUT/pmc_copy_fetch -o run -- "
                       "python3 $R/bench.py --copy-calibration",
-    "pmc_copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/prof/pmc_copy_write -o run -- "
+    "pmc_copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d $OUT/pmc_copy_write -o run -- "
                       "python3 $R/bench.py --copy-calibration",
 }
 _BOX_WORKLOAD = "256^3 periodic box, random fields |v|<=0.6 (seed 3), T=1+-10%, eta/s=0.5 (bench.py defaults)"
@@ -243,8 +244,8 @@ def summarize_profiles(prof_root):
     calib = ("# calibration: a plain 4 GiB device copy (%s) reads FETCH_SIZE %.1f KiB and WRITE_SIZE %.1f KiB per "
              "launch,\n#   so bytes = FETCH_SIZE KiB * 1024 * %.4f and bytes = WRITE_SIZE KiB * 1024 * %.4f\n"
              % (ck, cf, cw, f_fetch, f_write))
-    head = "# commands (run from /tmp with TMPDIR=/tmp; R is the repository root):\n"
-    tail = "#   then, on any host: python bench.py --summarize-profiles $R/gpurun_out/prof\n"
+    head = "# commands (run from /tmp with TMPDIR=/tmp; R is the repository root, OUT an output directory):\n"
+    tail = "#   then, on any host: python bench.py --summarize-profiles $OUT\n"
     written = []
     times = _dispatch_times(os.path.join(prof_root, "trace"))
     fetch = _dispatch_counters(os.path.join(prof_root, "pmc_fetch"), "FETCH_SIZE")
@@ -665,8 +666,8 @@ def _oracle_box_worker(job):
     return edge ** 3 * steps, dt
 
 
-# host cores given to the CPU baseline's parallel leg: the GPU machine's CPU
-# share (os.cpu_count() reports the whole machine there)
+# host cores given to the CPU baseline's parallel leg: the CPU share of one
+# GPU on a shared node (os.cpu_count() may report the whole machine)
 CPU_WORKERS = 16
 
 
