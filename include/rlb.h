@@ -257,8 +257,11 @@ int rlb_set_walls(rlb_solver *s, const uint8_t *solid, void *d_buf, size_t bytes
  * per tube, launched longest-work-first, whose wavefronts take the tube's
  * (step, chunk) work in order and wait only for the neighbouring chunks'
  * previous step (float64 tubes above 786,432 cells: a workgroup barrier
- * between steps instead).  Tubes never interact; a failure (status flag)
- * stays in its tube. */
+ * between steps instead).  Every such wait is bounded: after about 0.1 s it
+ * gives up and raises RLB_FLAG_STALL in its tube (never expected; the
+ * environment variable RLB_TUBE_SPIN_LIMIT, read by rlb_batch_step, lowers
+ * the bound to that many polls, for tests of that path).  Tubes never
+ * interact; a failure (status flag) stays in its tube. */
 typedef struct rlb_tube {
   int32_t n;        /* cells along z, 1 .. 4,194,304 (2^22)                */
   int32_t tau_mode; /* RLB_TAU_FIXED or RLB_TAU_ETA_S                       */

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -894,6 +895,7 @@ int rlb_batch_create(rlb_batch **out, const rlb_tube *tubes, int32_t ntubes, int
     d.n = tubes[j].n;
     d.cur = 0;
     d.mode = tubes[j].tau_mode == RLB_TAU_ETA_S ? 1 : 0;
+    d.spin_limit = 0;
     d.tau = tubes[j].tau;
     d.eta_s = tubes[j].eta_s;
   }
@@ -977,6 +979,10 @@ int rlb_batch_step(rlb_batch *b, const int64_t *steps) {
   }
   if (active == 0) return RLB_OK;
   std::vector<int64_t> rem(steps, steps + b->ntubes);
+  // tests of the stall path bound the kernel's waits to a few polls
+  const char *env = std::getenv("RLB_TUBE_SPIN_LIMIT");
+  const int32_t spin_limit = env ? std::max(0, std::atoi(env)) : 0;
+  for (int j = 0; j < b->ntubes; ++j) b->desc[j].spin_limit = spin_limit;
   // one launch per round: each tube takes as many of its remaining steps as
   // keep its (step, chunk) items of the launch below 2^31 (a single round
   // unless a run is very long)
@@ -1469,6 +1475,7 @@ int tubes_advance(rlb_server *sv, int prec, int order, bool &issued) {
     d.n = q->r.nz;
     d.cur = q->cur;
     d.mode = q->r.tau_mode == RLB_TAU_ETA_S ? 1 : 0;
+    d.spin_limit = 0;
     d.tau = q->r.tau;
     d.eta_s = q->r.eta_s;
     sv->h_order[p][k++] = q->slot;

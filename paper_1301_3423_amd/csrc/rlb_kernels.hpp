@@ -421,7 +421,7 @@ struct TubeDesc {
   int32_t n;      // cells along z
   int32_t cur;    // buffer holding the current state
   int32_t mode;   // 0 fixed tau, 1 tau from eta/s
-  int32_t pad;
+  int32_t spin_limit; // polls a wait may take before it gives up; 0: TUBE_SPIN_LIMIT
   double tau, eta_s;
 };
 
@@ -553,6 +553,7 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
   if (threadIdx.x == 0) next_ = 0;
   __syncthreads();
   const unsigned total = static_cast<unsigned>(d.steps) * nch;
+  const int spin_limit = d.spin_limit > 0 ? d.spin_limit : TUBE_SPIN_LIMIT;
   for (;;) {
     unsigned k = 0;
     if (lane == 0) k = atomicAdd(&next_, 1u);
@@ -562,14 +563,14 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
     const unsigned c = k - st * nch;
     int first, count;
     chunk_reach<CH>(static_cast<int>(c), static_cast<int>(nch), d.n, first, count);
-    const uint8_t need = static_cast<uint8_t>(st);
+      const uint8_t need = static_cast<uint8_t>(st);
     int spins = 0;
     for (;;) {
       bool ready = true;
       for (int q = 0, cq = first; q < count; ++q, cq = cq + 1 == static_cast<int>(nch) ? 0 : cq + 1)
         ready = ready && step_reached(done, cq, need);
       if (ready) break;
-      if (++spins >= TUBE_SPIN_LIMIT) {
+      if (++spins >= spin_limit) {
         flags |= FLAG_TUBE_SYNC; // never expected: give up the wait, keep going, report
         break;
       }

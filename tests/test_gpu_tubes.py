@@ -153,3 +153,23 @@ def test_tube_beyond_the_dataflow_flags_takes_the_barrier_kernel():
         err = field_errors(b.read_tube(j), s.read_fields())
         assert b.status(j) == (0, 3)
         assert max(err.values()) < 1e-13, (n, err)
+
+
+def test_stalled_wait_is_flagged_and_the_launch_ends(monkeypatch):
+    """The kernel's waits for neighbouring chunks are bounded.  With the bound
+    lowered to one poll (RLB_TUBE_SPIN_LIMIT=1, read by rlb_batch_step), the
+    waits that do not succeed at once give up: the launch still ends and the
+    tube reports RLB_FLAG_STALL (its fields are then not to be trusted).
+    Without the variable the same run is clean."""
+    f = inputs.shock_tube(100, 1.0, 0.8)      # two float32 chunks: wavefronts wait across steps
+    monkeypatch.setenv("RLB_TUBE_SPIN_LIMIT", "1")
+    b = rlb.Batch([dict(n=100, tau=0.9)], precision="mixed")
+    b.init_tube(0, *f)
+    b.step(50)
+    flags, t = b.status(0)
+    assert t == 50 and flags & rlb.FLAG_STALL
+    monkeypatch.delenv("RLB_TUBE_SPIN_LIMIT")
+    c = rlb.Batch([dict(n=100, tau=0.9)], precision="mixed")
+    c.init_tube(0, *f)
+    c.step(50)
+    assert c.status(0) == (0, 50)
