@@ -497,8 +497,8 @@ __device__ __forceinline__ void tube_cell_step(const S *__restrict__ in, S *__re
   for (int s = -MAXD; s <= MAXD; ++s) zo[s + MAXD] = static_cast<int>(tile_elem<M, S>(wrap_back(zc, s, g.nz)));
   const int own = static_cast<int>(tile_elem<M, S>(zc));
   S f[M::Q];
-  // loads at raised priority, as in the row kernel (batch of 512 tubes:
-  // 4306 -> 4465 MLUPS)
+  // loads at raised priority (512-tube batch in the earlier form with a
+  // barrier per step: 4306 -> 4465 MLUPS; the same time either way now)
   __builtin_amdgcn_s_setprio(3);
   static_for<0, M::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -563,7 +563,7 @@ k_tubes(S *__restrict__ base, const TubeDesc *__restrict__ desc, const int *__re
     const unsigned c = k - st * nch;
     int first, count;
     chunk_reach<CH>(static_cast<int>(c), static_cast<int>(nch), d.n, first, count);
-      const uint8_t need = static_cast<uint8_t>(st);
+    const uint8_t need = static_cast<uint8_t>(st);
     int spins = 0;
     for (;;) {
       bool ready = true;
