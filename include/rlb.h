@@ -313,8 +313,9 @@ void rlb_batch_destroy(rlb_batch *b);
  * for boxes), each advancing on its own: when a stream has finished its last
  * work, its finished requests are read back, freed and reported by
  * rlb_server_poll, and its next work is issued: each of its boxes by
- * chunk_steps * max(1, 262144 / cells) steps (replays of a hipGraph of
- * chunk_steps launches; the last issue may end with fewer), or each of its
+ * 20 * chunk_steps * max(1, 262144 / cells) steps (replays of a hipGraph of
+ * chunk_steps launches; the last issue may end with fewer; a long tube run
+ * as a box by chunk_steps * max(1, 262144 / nz)), or each of its
  * tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all resident
  * tubes of one precision and model in one persistent launch.  Tubes of 2048
  * cells or more run as 1 x 1 x nz boxes (box kernels, which spread a step
