@@ -1,9 +1,10 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py
 times, on sampled cells the oracle can compute one by one: after k steps a
 cell depends only on cells within 6k (the largest displacement is 6), so the
-oracle runs a periodic (12k+1)^3 window of the initial fields centred on the
-sample and its centre cell is exact.  Samples include the box corners, so
-the periodic wrap is exercised."""
+oracle runs a periodic window of the initial fields of edge 12k + 1 + 2r
+centred on a sample, and the (2r + 1)^3 cells around its centre are exact.
+Samples include the box corners (the periodic wrap) and a cube across the
+x boundary between storage tiles."""
 import numpy as np
 import pytest
 
@@ -14,17 +15,19 @@ from paper_1301_3423_amd import inputs, rlb
 pytestmark = pytest.mark.gpu
 
 K = 2                      # steps
-W = 12 * K + 1             # window edge
+RIN = 3                    # half edge of the exact cube compared around a sample
+H = 6 * K + RIN            # half edge of the oracle window
+W = 2 * H + 1              # window edge
 
 
 def _window(a, c):
     """Periodic window of edge W centred on cell c = (z, y, x)."""
-    idx = [np.arange(ci - 6 * K, ci + 6 * K + 1) % n for ci, n in zip(c, a.shape)]
+    idx = [np.arange(ci - H, ci + H + 1) % n for ci, n in zip(c, a.shape)]
     return a[np.ix_(*idx)]
 
 
 def _samples(edge, rng, count=6):
-    pts = [(0, 0, 0), (edge - 1, edge - 1, edge - 1), (edge // 2, 0, edge - 1)]
+    pts = [(0, 0, 0), (edge - 1, edge - 1, edge - 1), (edge // 2, 0, edge - 1), (edge // 3, 1, 64)]
     while len(pts) < count:
         pts.append(tuple(int(v) for v in rng.integers(0, edge, 3)))
     return pts
@@ -41,7 +44,7 @@ def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed, ord
     from oracle.lattice import model_lattice
     if order == 2:
         lat = model_lattice(2)
-    note("full size %d^3 %s order %d, %d steps" % (edge, precision, order, K))
+    note("full size %d^3 %s order %d, %d steps, %d^3 cells around each sample" % (edge, precision, order, K, 2 * RIN + 1))
     fields = inputs.random_box(edge, edge, edge, vmax, seed)
     s = rlb.Solver(edge, edge, edge, precision=precision, eta_s=eta_s, order=order)
     s.init_fields(*fields)
@@ -53,22 +56,25 @@ def test_sampled_cells_at_full_size(lat, edge, precision, vmax, eta_s, seed, ord
     tol = 1e-12 if precision == "fp64" else 1e-5
     rng = np.random.default_rng(edge)
     worst = 0.0
-    for c in _samples(edge, rng):
+    inner = np.arange(H - RIN, H + RIN + 1)
+    pts = _samples(edge, rng)
+    for c in pts:
         win = [_window(a, c) for a in fields]
         o = orlb.Solver(W, W, W, lat=lat, eta_s=eta_s, order=order)
         o.init_fields(*win)
         o.step(K)
         ref = o.read_fields()
-        mid = (6 * K) * W * W + (6 * K) * W + 6 * K
-        flat = c[0] * edge * edge + c[1] * edge + c[2]
-        U0 = ref["U"][0, mid]
-        errs = [abs(out["n"][flat] - ref["n"][mid]) / ref["n"][mid],
-                abs(out["eps"][flat] - ref["eps"][mid]) / ref["eps"][mid],
-                abs(out["P"][flat] - ref["P"][mid]) / ref["P"][mid]] + \
-               [abs(out["U"][j, flat] - ref["U"][j, mid]) / U0 for j in range(4)]
+        # the exact cube: window cells H - RIN .. H + RIN on each axis, the
+        # box cells c - RIN .. c + RIN (periodic)
+        mids = np.ravel(inner[:, None, None] * W * W + inner[None, :, None] * W + inner[None, None, :])
+        gz, gy, gx = [np.arange(ci - RIN, ci + RIN + 1) % edge for ci in c]
+        flat = np.ravel(gz[:, None, None] * edge * edge + gy[None, :, None] * edge + gx[None, None, :])
+        U0 = ref["U"][0, mids]
+        errs = [np.max(np.abs(out[k][flat] - ref[k][mids]) / ref[k][mids]) for k in ("n", "eps", "P")] + \
+               [np.max(np.abs(out["U"][j, flat] - ref["U"][j, mids]) / U0) for j in range(4)]
         worst = max(worst, max(errs))
         assert max(errs) <= tol, (c, errs)
-    note("worst sampled relative error %.2e" % worst)
+    note("worst relative error over %d cells: %.2e" % (len(pts) * (2 * RIN + 1) ** 3, worst))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
