@@ -322,9 +322,9 @@ void rlb_batch_destroy(rlb_batch *b);
  * over many CUs, where a persistent tube launch gives a tube one CU), on
  * the tube stream of their precision.
  * The four streams should each have a hardware queue: a process that has
- * other busy streams should raise GPU_MAX_HW_QUEUES (HIP's default is 4).  A request's result does not depend on what else is
- * resident (the kernels never mix requests).  Times are seconds since the
- * server was created. */
+ * other busy streams should raise GPU_MAX_HW_QUEUES (HIP's default is 4).
+ * A request's result does not depend on what else is resident (the kernels
+ * never mix requests).  Times are seconds since the server was created. */
 #define RLB_REQ_TUBE 0 /* 1 x 1 x nz lattice (nx = ny = 1)                */
 #define RLB_REQ_BOX 1  /* nx x ny x nz periodic box                        */
 
