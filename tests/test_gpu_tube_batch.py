@@ -2,7 +2,7 @@
 200-4000, temperature ratios 1.1-2, eta/s in {0.01, ..., 0.5}), 500 steps in
 one persistent launch -- the launch the benchmark times -- against the
 oracle's fields of every tube (golden/oracle_tube_batch.npz, written by
-make_tube_batch.py from the oracle alone) on 32 sampled cells per tube,
+make_tube_batch.py from the oracle alone) on 28-32 sampled cells per tube,
 each relative to the largest value of its field over the whole tube (the
 4-velocity as a 4-vector).  Tubes the oracle flags non-physical must be
 flagged on the GPU and only those.  The float64 bar of a tube is 1e-12, or
