@@ -1428,8 +1428,8 @@ int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
 
 // Steps a resident box takes per issue on its stream: BOX_ISSUE_CHUNKS
 // chunks for boxes of BOX_ROUND_CELLS cells or more, proportionally more (in
-// whole chunks) for smaller boxes; a long tube run as a box takes one chunk
-// per BOX_ROUND_CELLS of that.  Long issues keep a box from being
+// whole chunks) for smaller boxes; a long tube run as a box takes
+// max(1, BOX_ROUND_CELLS / n) chunks of its n cells.  Long issues keep a box from being
 // interleaved with every box that arrives during its run (a box stream then
 // works almost first come, first served; the two box streams take boxes by
 // least work left).  On the serving mix at a fixed 22.3 requests/s with
