@@ -107,6 +107,48 @@ def copy_bandwidth():
     return 2 * n / (ms * 1e-3) / 1e9
 
 
+def stream_ceiling():
+    """What this device streams in practice: the best of a few launch shapes
+    of the hand-written copy, read-only and write-only kernels in
+    libstream_probe.so over 4 GiB buffers (GB/s: bytes read plus written per
+    second; the copy counts both)."""
+    import ctypes
+    import torch
+    from paper_1301_3423_amd import build as _b
+    if not os.path.exists(_b.PROBE_OUT):
+        raise RuntimeError("libstream_probe.so is not built (python -m paper_1301_3423_amd.build)")
+    lib = ctypes.CDLL(_b.PROBE_OUT)
+    f = lib.stream_probe_ms
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    n = 4 << 30
+    grids = (2048, 8192)
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(max(grids) * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    out = {}
+    for kind, name, factor in ((0, "copy", 2), (1, "copy_nontemporal", 2), (2, "read", 1), (3, "write", 1)):
+        best = None
+        for unroll in (1, 2, 4, 8):
+            for grid in grids:
+                ms = f(kind, unroll, grid, src.data_ptr(), dst.data_ptr(), sink.data_ptr(), n, 4, st.cuda_stream)
+                if ms <= 0:
+                    raise RuntimeError("stream probe failed (kind %d, unroll %d, grid %d): %g" % (kind, unroll, grid, ms))
+                gbs = factor * n / (ms * 1e-3) / 1e9
+                if best is None or gbs > best[0]:
+                    best = (gbs, unroll, grid)
+        out[name + "_GBps"] = round(best[0], 1)
+        out[name + "_shape"] = "%d x 16 B in flight per thread, %d workgroups of 256" % (best[1], best[2])
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    out["note"] = ("hand-written streaming kernels over 4 GiB (csrc/stream_probe.hip), the best launch shape of "
+                   "1-8 16-byte vectors in flight per thread and 2048 or 8192 workgroups, shortest of 4 launches")
+    return out
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: 4 GiB read + 4 GiB
     written per launch, three launches."""
@@ -724,6 +766,9 @@ def main():
     edge = args.edge
     copy_gbs = copy_bandwidth()
     print("bench: plain copy %.0f GB/s" % copy_gbs, file=sys.stderr, flush=True)
+    ceiling = stream_ceiling()
+    print("bench: streaming kernels: copy %.0f GB/s, read %.0f GB/s, write %.0f GB/s"
+          % (ceiling["copy_GBps"], ceiling["read_GBps"], ceiling["write_GBps"]), file=sys.stderr, flush=True)
     print("bench: generating %d^3 fields" % edge, file=sys.stderr, flush=True)
     fields = inputs.random_box(edge, edge, edge, args.vmax, seed=3)
     print("bench: mixed precision", file=sys.stderr, flush=True)
@@ -854,7 +899,10 @@ def main():
         "status_flags": mixed["flags"],
         "conservation_drift": mixed["conservation_drift"],
         "copy_GBps": round(copy_gbs, 1),
+        "stream_ceiling": ceiling,
     }
+    best_copy = max(ceiling["copy_GBps"], ceiling["copy_nontemporal_GBps"])
+    ceiling["mixed_step_over_best_copy"] = round(line["roofline"]["achieved"] / best_copy, 3)
     if fp64 is not None:
         line["fp64"] = {"value": round(fp64["mlups"], 2), "unit": "MLUPS", "dtype": "f64",
                         "ms_per_step": round(fp64["ms_per_step"], 4),

@@ -11,6 +11,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 REPO = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "rlb_capi.hip")
 OUT = os.path.join(PKG, "librlb.so")
+# streaming-ceiling kernels for the benchmark (not part of the method)
+PROBE_SRC = os.path.join(PKG, "csrc", "stream_probe.hip")
+PROBE_OUT = os.path.join(PKG, "libstream_probe.so")
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -54,8 +57,8 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(extra=(), out=OUT, verbose=False):
-    cmd = [hipcc()] + HIP_FLAGS + list(extra) + [SRC, "-o", out + ".tmp"]
+def build(extra=(), out=OUT, verbose=False, src=SRC):
+    cmd = [hipcc()] + HIP_FLAGS + list(extra) + [src, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -66,5 +69,10 @@ def build(extra=(), out=OUT, verbose=False):
     return out
 
 
+def build_probe(verbose=False):
+    return build(out=PROBE_OUT, verbose=verbose, src=PROBE_SRC)
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

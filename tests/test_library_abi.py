@@ -159,3 +159,22 @@ def test_walls_bytes_counts_bounce_back_links(order):
     assert rlb.lib().rlb_walls_bytes(order, nx, ny, nz, ctypes.c_void_p(full.ctypes.data)) == 0
     assert rlb.lib().rlb_walls_bytes(order, nx, ny, nz, None) == 0
     assert rlb.lib().rlb_walls_bytes(5, nx, ny, nz, ctypes.c_void_p(solid.ctypes.data)) == 0
+
+
+def test_stream_probe_library_loads_and_rejects_bad_arguments():
+    """The benchmark's streaming probe (not part of the method) is built
+    beside the library; its argument checks run before any device call."""
+    import ctypes
+    from paper_1301_3423_amd import build as _b
+    if not os.path.exists(_b.PROBE_OUT):
+        pytest.skip("libstream_probe.so not built")
+    f = ctypes.CDLL(_b.PROBE_OUT).stream_probe_ms
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    assert f(0, 4, 64, 16, 16, None, 0, 1, None) == -1.0      # no bytes
+    assert f(0, 4, 64, 16, 16, None, 24, 1, None) == -1.0     # not a multiple of 16
+    assert f(0, 3, 64, 16, 16, None, 32, 1, None) == -1.0     # unroll not 1, 2, 4 or 8
+    assert f(4, 4, 64, 16, 16, None, 32, 1, None) == -1.0     # no such kind
+    assert f(2, 4, 64, 16, None, None, 32, 1, None) == -1.0   # read without a sink
+    assert f(0, 4, 64, None, 16, None, 32, 1, None) == -1.0   # copy without a source
