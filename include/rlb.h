@@ -313,7 +313,7 @@ void rlb_batch_destroy(rlb_batch *b);
  * for boxes), each advancing on its own: when a stream has finished its last
  * work, its finished requests are read back, freed and reported by
  * rlb_server_poll, and its next work is issued: each of its boxes by
- * 20 * chunk_steps * max(1, 262144 / cells) steps (replays of a hipGraph of
+ * 40 * chunk_steps * max(1, 262144 / cells) steps (replays of a hipGraph of
  * chunk_steps launches; the last issue may end with fewer; a long tube run
  * as a box by chunk_steps * max(1, 262144 / nz)), or each of its
  * tubes by max(chunk_steps, chunk_steps * 8192 / nz) steps, all resident

@@ -1429,16 +1429,19 @@ int box_advance(rlb_server *sv, ServeReq *q, int64_t steps) {
 // Steps a resident box takes per issue on its stream: BOX_ISSUE_CHUNKS
 // chunks for boxes of BOX_ROUND_CELLS cells or more, proportionally more (in
 // whole chunks) for smaller boxes; a long tube run as a box takes
-// max(1, BOX_ROUND_CELLS / n) chunks of its n cells.  Long issues keep a box from being
-// interleaved with every box that arrives during its run (a box stream then
-// works almost first come, first served; the two box streams take boxes by
-// least work left).  On the serving mix at a fixed 22.3 requests/s with
-// 50-step chunks, box issues of 1 chunk gave a p99 latency of 2.98-3.07 s
-// (boxes 3.3-3.6 s, tubes 0.44 s), issues of 20 chunks 1.83-2.01 s (boxes
-// 2.05-2.24 s, tubes 0.54 s), with p50 0.07 s both ways.  Tube rounds stay
-// at one chunk: 1000-step tube rounds raised the tubes' p99 to 0.6 s.
+// max(1, BOX_ROUND_CELLS / n) chunks of its n cells.  Long issues keep a
+// box from being interleaved with every box that arrives during its run (a
+// box stream then works almost first come, first served; the two box
+// streams take boxes by least work left).  On the serving mix at a fixed
+// 22.3 requests/s with 50-step chunks, the p99 latency was 2.98-3.07 s with
+// box issues of 1 chunk, 2.06 s with 5, 2.06-2.09 s with 10, 1.83-2.04 s with
+// 20 and 1.82 s with 40 (boxes 3.3-3.6, 2.5-2.6, 2.4, 2.05-2.24 and 2.05 s;
+// tubes 0.44-0.54 s; p50 0.07 s throughout).  With 40 chunks of 50 steps
+// every box of that mix (at most 1000 steps) runs to the end in one issue.
+// Tube rounds stay at one chunk: 1000-step tube rounds raised the tubes'
+// p99 to 0.6 s.
 constexpr int64_t BOX_ROUND_CELLS = 262144; // 64^3
-constexpr int64_t BOX_ISSUE_CHUNKS = 20;
+constexpr int64_t BOX_ISSUE_CHUNKS = 40;
 
 int64_t box_round_steps(const rlb_server *sv, const ServeReq *q) {
   int64_t chunks = std::max<int64_t>(1, BOX_ROUND_CELLS / std::max<int64_t>(request_cells(q->r), 1));
